@@ -1,0 +1,200 @@
+/*
+ * mcl.h -- C ABI of the MI355X (gfx950) belief-tensor localization filter.
+ *
+ * The filter keeps a dense belief tensor B[theta][y][x] over every robot pose
+ * of an occupancy grid and updates it from odometry and, optionally, range
+ * scans, as in Peng and Weikersdorfer, "Map as The Hidden Sensor: Fast
+ * Odometry-Based Global Localization" (arXiv 1910.00572), Sec. III and Alg. 1.
+ *
+ * Conventions used throughout
+ *   - Grid cell (i, j) has column i (world x, metres = i * cell_m) and row j
+ *     (world y).  Heading channel k of n_theta represents the world heading
+ *     k * 2 pi / n_theta + theta_offset (Sec. III-A, belief tensor), where
+ *     theta_offset is the running sum of odometry heading increments.
+ *   - Odometry increments (u, v, w) are robot-frame: u forward, v to the
+ *     left (metres), w counter-clockwise heading change (radians).
+ *   - Host arrays are row-major and dense: occupancy[j * W + i],
+ *     belief[(k * H + j) * W + i].
+ *   - All device memory is owned by the caller.  The library never allocates
+ *     device memory: the caller queries a workspace size, allocates that many
+ *     bytes of device memory (256-byte aligned) and hands it over; the handle
+ *     uses it until it is destroyed.  Host inputs are copied during the call.
+ *   - Every call returns an mcl_status.  Argument errors are detected before
+ *     any work is enqueued and leave the state unchanged; mcl_last_error()
+ *     then holds a message (per thread).  Conditions found on the device (all
+ *     probability mass removed, a HIP error) are sticky and are reported by
+ *     the next synchronising call (mcl_normalize, mcl_read_belief,
+ *     mcl_get_info with sync = 1).
+ *   - "async" calls only enqueue work on the handle's stream and return.
+ *   - A handle is not thread-safe; drive each handle from one host thread.
+ */
+#ifndef MCL_H_
+#define MCL_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  MCL_OK = 0,
+  MCL_EINVAL = 1,      /* bad argument; nothing was enqueued */
+  MCL_ENOMEM = 2,      /* workspace smaller than the queried size */
+  MCL_EDEGENERATE = 3, /* a step removed all probability mass (belief kept) */
+  MCL_EDEVICE = 4,     /* a HIP runtime error; message in mcl_last_error() */
+  MCL_ESTATE = 5       /* call not valid in the current state (e.g. no range table) */
+} mcl_status;
+
+typedef enum { MCL_F32 = 0, MCL_BF16 = 1, MCL_F16 = 2 } mcl_dtype;
+
+/* Map-level flags (Alg. 1).  Default MCL_MASK_BEFORE_BLUR | MCL_WALL_NORMALIZE. */
+enum {
+  MCL_MASK_BEFORE_BLUR = 1u, /* multiply by the traversability map after the warp */
+  MCL_WALL_NORMALIZE = 2u,   /* divide by the kernel activation G(B_0) after the blur */
+  MCL_SUBCELL_GATE = 4u,     /* accumulate motion until it reaches one cell (Alg. 1 IF) */
+  MCL_SCAN_F32 = 8u          /* scan cross term on FP32 operands instead of BF16 */
+};
+
+typedef struct {
+  int32_t width, height;        /* W, H >= 1 */
+  double cell_m;                /* cell size in metres, > 0 */
+  const uint8_t* occupancy;     /* host, H*W, nonzero = occupied; copied */
+  const float* range_table;     /* host, nullable: expected range in metres from the centre
+                                   of each cell along world direction d * 2 pi / n_dirs,
+                                   layout [(j*W + i) * n_dirs + d]; copied and quantised */
+  int32_t n_dirs;               /* directions per cell (required if range_table != NULL) */
+  double max_range_m;           /* sensor range; ranges are quantised to max_range_m / 256 */
+} mcl_map_desc;
+
+typedef struct {
+  int32_t n_theta;              /* heading channels, 1 .. 360 */
+  double sigma_xy_cells;        /* motion-noise std-dev in x and y, cells, >= 0 */
+  double sigma_theta_bins;      /* motion-noise std-dev in theta, bins, >= 0 */
+  int32_t radius_xy;            /* blur half-width in cells; < 0 => ceil(3 sigma) */
+  int32_t radius_theta;         /* blur half-width in bins;  < 0 => ceil(3 sigma) */
+  mcl_dtype storage;            /* belief storage type; arithmetic is always FP32 */
+  uint32_t flags;               /* MCL_* flags above */
+} mcl_params;
+
+typedef struct {
+  int32_t i, j, k;              /* grid cell and heading channel */
+  double x_m, y_m, theta_rad;   /* i*cell, j*cell, k*2pi/n_theta + theta_offset */
+  double prob;                  /* normalised probability of that state */
+} mcl_pose;
+
+typedef struct {
+  int32_t width, height, n_theta, pitch; /* device rows are `pitch` elements apart */
+  int32_t storage;              /* mcl_dtype */
+  int32_t radius;               /* blur radius the kernels run with */
+  int32_t tile_x, tile_y, theta_chunks, workgroups; /* launch shape of the step kernel */
+  int64_t steps;                /* odometry steps applied */
+  double theta_offset_rad;      /* running heading offset */
+  double log_norm;              /* sum over updates of ln(kept mass) (valid after a sync) */
+  int32_t status;               /* sticky device status (valid after a sync) */
+  const void* belief_device;    /* current stored belief (device, pitch layout, scaled) */
+  uint64_t state_bytes;         /* belief bytes one step reads (= bytes it writes) */
+} mcl_info;
+
+typedef struct mcl_map_s* mcl_map;
+typedef struct mcl_filter_s* mcl_filter;
+
+/* Thread-local message describing the last non-OK status. */
+const char* mcl_last_error(void);
+
+/* ---- map ------------------------------------------------------------------ */
+
+/* Device bytes a map needs for this description and these parameters
+ * (traversability, wall weights, and the quantised range table if given).
+ * Returns 0 if the arguments are invalid. */
+size_t mcl_map_workspace_bytes(const mcl_map_desc* desc, const mcl_params* params);
+
+/* Build a map: traversability M (Sec. III-A-3), the kernel activation
+ * G(B_0) and the post-blur weights M / G(B_0) (Alg. 1, last statement), and
+ * the range table quantised to centred counts of max_range/256 together with
+ * its per-cell sum of squares (dense scan update, eq. sensor update).  Uses
+ * sigma_xy / radius_xy / flags of `params`; the theta fields are ignored.
+ * `stream` is a hipStream_t (NULL = default stream).  Synchronous.
+ * The map must outlive every filter created on it. */
+mcl_status mcl_map_create(const mcl_map_desc* desc, const mcl_params* params, void* dev_ws,
+                          size_t ws_bytes, void* stream, mcl_map* out);
+void mcl_map_destroy(mcl_map map);
+
+/* ---- filter ---------------------------------------------------------------- */
+
+/* Device bytes a filter needs: two belief buffers (storage type, pitch
+ * layout), a one-slice FP32 staging area, reduction partials and the device
+ * scalars; plus an FP32 scan scratch when the map has a range table. */
+size_t mcl_filter_workspace_bytes(mcl_map map, const mcl_params* params);
+
+/* init_belief: create a filter on `map` (Sec. III-A, belief tensor).
+ * init_host == NULL: B_0 uniform over the free cells of every heading channel.
+ * Otherwise init_host is a host FP32 array of n_theta*H*W non-negative values
+ * (any scale; it is renormalised) that becomes B_0 (checkpoint resume).
+ * theta0_rad sets the running heading offset.  sigma_xy / radius_xy / flags
+ * must equal those the map was built with.  Synchronous. */
+mcl_status mcl_init_belief(mcl_map map, const mcl_params* params, void* dev_ws, size_t ws_bytes,
+                           void* stream, const float* init_host, double theta0_rad,
+                           mcl_filter* out);
+void mcl_filter_destroy(mcl_filter f);
+
+/* step_odometry (async): one odometry update, Alg. 1 followed by
+ * renormalisation (eq. sensor update's eta applied to the motion update):
+ * every channel k is warped bilinearly by R(theta_offset + k*2pi/n_theta)
+ * [u, v] (Sec. III-A-1), multiplied by M, blurred by the separable Gaussian
+ * (x, y zero-padded, theta circular; Sec. III-A-2), multiplied by
+ * M / G(B_0), and renormalised; then theta_offset += w.  With
+ * MCL_SUBCELL_GATE the motion is accumulated and applied once it reaches one
+ * cell.  EINVAL for non-finite input or |(u, v)| above 1e6 cells. */
+mcl_status mcl_step_odometry(mcl_filter f, double u_m, double v_m, double w_rad);
+
+/* apply_scan (async): dense observation update (eq. sensor update) with a
+ * per-beam Gaussian range model of std-dev sigma_m.  ranges_m holds n_beams
+ * host FP32 ranges; beam b points at heading(k) + b * 2 pi / n_beams.
+ * n_beams must equal the map's n_dirs; ESTATE if the map has no range table. */
+mcl_status mcl_apply_scan(mcl_filter f, const float* ranges_m, int32_t n_beams, double sigma_m);
+
+/* normalize (sync): rescale the stored belief in place so it sums to one
+ * (FP32, BF16) or peaks at one (FP16, whose range cannot hold a sum-one
+ * belief), and return the accumulated log-normaliser ln prod(kept mass)
+ * (eq. sensor update's eta) in *log_norm_out (nullable).  Reports sticky
+ * device errors. */
+mcl_status mcl_normalize(mcl_filter f, double* log_norm_out);
+
+/* read_belief (sync): copy the normalised FP32 belief (sums to one) into
+ * host_out (n_theta*H*W, nullable), the most probable state into *argmax
+ * (nullable; lowest flat index (k, j, i) wins ties; the belief map is the max
+ * over theta, Sec. III-A last paragraph), the running heading offset and the
+ * log-normaliser (both nullable).  Reports sticky device errors. */
+mcl_status mcl_read_belief(mcl_filter f, float* host_out, mcl_pose* argmax,
+                           double* theta_offset_rad, double* log_norm);
+
+/* export_belief (async): write the normalised FP32 belief into dev_out
+ * (device, n_theta*H*W dense) and, if dev_map_out != NULL, the belief map
+ * max_k B into dev_map_out (device, H*W). */
+mcl_status mcl_export_belief(mcl_filter f, float* dev_out, float* dev_map_out);
+
+/* scan_sqdist (async, diagnostic): the exact integer squared distance
+ * D[k][j][i] = sum_b (zq_b - rq(i, j, beam b of channel k))^2 between the
+ * quantised scan and the quantised table, as the scan update computes it
+ * (cross term on the matrix cores).  dev_out: device int32, n_theta*H*W. */
+mcl_status mcl_scan_sqdist(mcl_filter f, const float* ranges_m, int32_t n_beams,
+                           int32_t* dev_out);
+
+/* Launch shape, sizes and scalars.  sync != 0 waits for the stream first so
+ * log_norm and status are current. */
+mcl_status mcl_get_info(mcl_filter f, int sync, mcl_info* out);
+
+/* step_batch (async, serving): one odometry step for each of n filters, in
+ * as few launches as their storage types and radii allow, on `stream`
+ * (NULL = each filter's own stream must then be the same).  uvw holds 3
+ * doubles per filter.  Each filter's result is bitwise identical to calling
+ * mcl_step_odometry on it alone.  Filters must be distinct. */
+mcl_status mcl_step_batch(mcl_filter* const filters, const double* uvw, int32_t n, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MCL_H_ */

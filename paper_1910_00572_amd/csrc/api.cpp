@@ -1,0 +1,573 @@
+// Host side of the C ABI declared in include/mcl.h.
+//
+// Validates arguments, carves caller-provided device workspaces, computes the
+// per-step scalars in FP64 (taps, heading bookkeeping, sub-cell gate) and
+// enqueues the kernels on the handle's stream.  No device allocation happens
+// here; all per-state arithmetic runs in the HIP kernels.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "../../include/mcl.h"
+#include "mcl_internal.hpp"
+#include "scan.hpp"
+
+using namespace mcl;
+
+namespace {
+
+thread_local std::string g_err;
+
+mcl_status fail(mcl_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+mcl_status hip_fail(hipError_t e, const char* what) {
+  return fail(MCL_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIP_TRY(expr, what)                     \
+  do {                                          \
+    hipError_t e_ = (expr);                     \
+    if (e_ != hipSuccess) return hip_fail(e_, what); \
+  } while (0)
+
+int round_up(int x, int m) { return (x + m - 1) / m * m; }
+
+int resolve_radius(double sigma, int r) { return r >= 0 ? r : static_cast<int>(ceil(3.0 * sigma)); }
+
+void gaussian_taps(double sigma, int radius, double* g) {
+  double z = 0.0;
+  for (int m = -radius; m <= radius; ++m) {
+    const double v = sigma == 0.0 ? (m == 0 ? 1.0 : 0.0) : exp(-(m * (double)m) / (2.0 * sigma * sigma));
+    g[m + radius] = v;
+    z += v;
+  }
+  for (int i = 0; i <= 2 * radius; ++i) g[i] /= z;
+}
+
+size_t dtype_bytes(int dt) { return dt == MCL_F32 ? 4 : 2; }
+
+mcl_status check_params(const mcl_params* p, bool need_theta) {
+  if (!p) return fail(MCL_EINVAL, "params is NULL");
+  if (!(p->sigma_xy_cells >= 0.0) || !isfinite(p->sigma_xy_cells))
+    return fail(MCL_EINVAL, "sigma_xy_cells must be finite and >= 0");
+  const int rxy = resolve_radius(p->sigma_xy_cells, p->radius_xy);
+  if (rxy > kMaxRadius) return fail(MCL_EINVAL, "xy blur radius %d exceeds %d", rxy, kMaxRadius);
+  if (p->flags & ~0xFu) return fail(MCL_EINVAL, "unknown flags 0x%x", p->flags);
+  if (need_theta) {
+    if (p->n_theta < 1 || p->n_theta > kMaxTheta)
+      return fail(MCL_EINVAL, "n_theta must be in [1, %d]", kMaxTheta);
+    if (!(p->sigma_theta_bins >= 0.0) || !isfinite(p->sigma_theta_bins))
+      return fail(MCL_EINVAL, "sigma_theta_bins must be finite and >= 0");
+    const int rth = resolve_radius(p->sigma_theta_bins, p->radius_theta);
+    if (rth > kMaxRadius) return fail(MCL_EINVAL, "theta blur radius %d exceeds %d", rth, kMaxRadius);
+    if (p->storage < MCL_F32 || p->storage > MCL_F16) return fail(MCL_EINVAL, "unknown storage type");
+  }
+  return MCL_OK;
+}
+
+mcl_status check_desc(const mcl_map_desc* d) {
+  if (!d) return fail(MCL_EINVAL, "desc is NULL");
+  if (d->width < 1 || d->height < 1 || d->width > 65536 || d->height > 65536)
+    return fail(MCL_EINVAL, "map size %dx%d out of range", d->width, d->height);
+  if (!(d->cell_m > 0.0) || !isfinite(d->cell_m)) return fail(MCL_EINVAL, "cell_m must be > 0");
+  if (!d->occupancy) return fail(MCL_EINVAL, "occupancy is NULL");
+  if (d->range_table) {
+    if (d->n_dirs < 1 || d->n_dirs > kScanMaxDirs)
+      return fail(MCL_EINVAL, "n_dirs must be in [1, %d]", kScanMaxDirs);
+    if (!(d->max_range_m > 0.0) || !isfinite(d->max_range_m))
+      return fail(MCL_EINVAL, "max_range_m must be > 0");
+  }
+  return MCL_OK;
+}
+
+}  // namespace
+
+// ---- handles -------------------------------------------------------------------
+
+struct mcl_map_s {
+  int W = 0, H = 0, pitch = 0;
+  double cell = 0.0;
+  double sigma_xy = 0.0;
+  int rxy = 0;
+  uint32_t flags = 0;
+  hipStream_t stream = nullptr;
+  uint8_t* occ_dev = nullptr;
+  uint8_t* free8 = nullptr;
+  float* mpre = nullptr;
+  float* wt = nullptr;
+  int64_t n_free = 0;
+  ScanTable scan;  // quantised range table (scan.hpp)
+};
+
+struct StepShape {
+  int tx = 64, ty = 16, nt = 256, chunks = 1, chunk_len = 1, tiles_x = 1, tiles_y = 1;
+  int blocks() const { return tiles_x * tiles_y * chunks; }
+};
+
+struct mcl_filter_s {
+  mcl_map map = nullptr;
+  int T = 0;
+  int dtype = 0;
+  int radius = 1;
+  double sigma_th = 0.0;
+  int rth = 0;
+  hipStream_t stream = nullptr;
+  void* buf[2] = {nullptr, nullptr};
+  float* staging = nullptr;
+  double* partials = nullptr;
+  int n_partials = 0;
+  FilterDev* dev = nullptr;
+  float* scan_scratch = nullptr;
+  ScanWork scanw;
+  int64_t sstride = 0;
+  double theta = 0.0;
+  double acc_x = 0.0, acc_y = 0.0;
+  int64_t steps = 0;
+  StepShape shape;
+  float gxy[kMaxTaps] = {};
+  float gth[kMaxTaps] = {};
+};
+
+namespace {
+
+constexpr int kReduceBlocks = 1024;
+
+StepShape choose_shape(int W, int H, int T, int R) {
+  StepShape s;
+  int sh[4] = {64, 16, 256, 0};
+  if (const char* env = getenv("MCL_STEP_SHAPE")) {
+    int a = 0, b = 0, c = 0, d = 0;
+    if (sscanf(env, "%d,%d,%d,%d", &a, &b, &c, &d) >= 3) {
+      sh[0] = a;
+      sh[1] = b;
+      sh[2] = c;
+      sh[3] = d;
+    }
+  }
+  s.tx = sh[0];
+  s.ty = sh[1];
+  s.nt = sh[2];
+  s.tiles_x = (W + s.tx - 1) / s.tx;
+  s.tiles_y = (H + s.ty - 1) / s.ty;
+  const int tiles = s.tiles_x * s.tiles_y;
+  int chunks = sh[3];
+  if (chunks <= 0) {
+    // aim for at least two workgroups per compute unit; every chunk keeps at
+    // least 2R+1 channels so the recomputed halo stays below its own size
+    chunks = std::max(1, (512 + tiles - 1) / tiles);
+    chunks = std::min(chunks, std::max(1, T / (2 * R + 1)));
+  }
+  chunks = std::min(chunks, T);
+  s.chunk_len = (T + chunks - 1) / chunks;
+  s.chunks = (T + s.chunk_len - 1) / s.chunk_len;
+  return s;
+}
+
+StepArgs make_step_args(mcl_filter f) {
+  StepArgs a = {};
+  const mcl_map m = f->map;
+  a.buf[0] = f->buf[0];
+  a.buf[1] = f->buf[1];
+  a.mpre = m->mpre;
+  a.wt = m->wt;
+  a.partials = f->partials;
+  a.dev = f->dev;
+  a.W = m->W;
+  a.H = m->H;
+  a.pitch = m->pitch;
+  a.n_theta = f->T;
+  a.tiles_x = f->shape.tiles_x;
+  a.tiles_y = f->shape.tiles_y;
+  a.chunks = f->shape.chunks;
+  a.chunk_len = f->shape.chunk_len;
+  a.sstride = f->sstride;
+  a.dtheta = 2.0 * M_PI / f->T;
+  for (int i = 0; i < kMaxTaps; ++i) {
+    a.gxy[i] = f->gxy[i];
+    a.gth[i] = f->gth[i];
+  }
+  return a;
+}
+
+ReduceArgs make_reduce_args(mcl_filter f, int mode, double factor) {
+  ReduceArgs r = {};
+  r.buf[0] = f->buf[0];
+  r.buf[1] = f->buf[1];
+  r.partials = f->partials;
+  r.dev = f->dev;
+  r.W = f->map->W;
+  r.H = f->map->H;
+  r.pitch = f->map->pitch;
+  r.n_theta = f->T;
+  r.sstride = f->sstride;
+  r.factor = factor;
+  r.mode = mode;
+  return r;
+}
+
+mcl_status read_dev(mcl_filter f, FilterDev* out) {
+  HIP_TRY(hipMemcpyAsync(out, f->dev, sizeof(FilterDev), hipMemcpyDeviceToHost, f->stream), "read scalars");
+  HIP_TRY(hipStreamSynchronize(f->stream), "synchronize");
+  return MCL_OK;
+}
+
+// Carve (or measure, when ws == nullptr) a filter workspace.
+size_t carve_filter(mcl_filter f, void* ws, const mcl_map m, const mcl_params* p) {
+  Carver c(ws);
+  const int64_t sstride = static_cast<int64_t>(m->H) * m->pitch;
+  const size_t n = static_cast<size_t>(sstride) * p->n_theta;
+  const size_t eb = dtype_bytes(p->storage);
+  void* b0 = c.take(n * eb);
+  void* b1 = c.take(n * eb);
+  float* staging = static_cast<float*>(c.take(static_cast<size_t>(m->W) * m->H * sizeof(float)));
+  const int R = std::max(1, std::max(m->rxy, resolve_radius(p->sigma_theta_bins, p->radius_theta)));
+  const StepShape sh = choose_shape(m->W, m->H, p->n_theta, R);
+  const int np = std::max(sh.blocks(), std::max(kReduceBlocks, kScanMaxBlocks(m->W, m->H, m->pitch)));
+  double* partials = static_cast<double*>(c.take(static_cast<size_t>(np) * 3 * sizeof(double)));
+  FilterDev* dev = static_cast<FilterDev*>(c.take(sizeof(FilterDev)));
+  float* scratch = nullptr;
+  if (m->scan.n_dirs > 0) scratch = static_cast<float*>(c.take(n * sizeof(float)));
+  void* scanw = c.take(scan_work_bytes(p->n_theta, m->scan.kpad));
+  if (f) {
+    f->buf[0] = b0;
+    f->buf[1] = b1;
+    f->staging = staging;
+    f->partials = partials;
+    f->n_partials = np;
+    f->dev = dev;
+    f->scan_scratch = scratch;
+    f->scanw = scan_work_carve(scanw, p->n_theta, m->scan.kpad);
+    f->sstride = sstride;
+    f->shape = sh;
+    f->radius = R;
+  }
+  return c.off;
+}
+
+size_t carve_map(mcl_map m, void* ws, const mcl_map_desc* d, const mcl_params* p) {
+  Carver c(ws);
+  const int pitch = round_up(d->width, kRowAlign);
+  const size_t plane = static_cast<size_t>(d->height) * pitch;
+  uint8_t* occ = static_cast<uint8_t*>(c.take(static_cast<size_t>(d->width) * d->height));
+  uint8_t* free8 = static_cast<uint8_t*>(c.take(plane));
+  float* mpre = static_cast<float*>(c.take(plane * sizeof(float)));
+  float* wt = static_cast<float*>(c.take(plane * sizeof(float)));
+  ScanTable st = scan_table_carve(c, d, pitch, (p->flags & MCL_SCAN_F32) != 0);
+  if (m) {
+    m->pitch = pitch;
+    m->occ_dev = occ;
+    m->free8 = free8;
+    m->mpre = mpre;
+    m->wt = wt;
+    m->scan = st;
+  }
+  return c.off;
+}
+
+}  // namespace
+
+// ---- ABI -----------------------------------------------------------------------
+
+extern "C" {
+
+const char* mcl_last_error(void) { return g_err.c_str(); }
+
+size_t mcl_map_workspace_bytes(const mcl_map_desc* desc, const mcl_params* params) {
+  if (check_desc(desc) != MCL_OK || check_params(params, false) != MCL_OK) return 0;
+  return carve_map(nullptr, nullptr, desc, params);
+}
+
+mcl_status mcl_map_create(const mcl_map_desc* d, const mcl_params* p, void* ws, size_t ws_bytes,
+                          void* stream, mcl_map* out) {
+  if (!out) return fail(MCL_EINVAL, "out is NULL");
+  mcl_status st = check_desc(d);
+  if (st != MCL_OK) return st;
+  if ((st = check_params(p, false)) != MCL_OK) return st;
+  if (!ws) return fail(MCL_EINVAL, "workspace is NULL");
+  const size_t need = carve_map(nullptr, nullptr, d, p);
+  if (ws_bytes < need) return fail(MCL_ENOMEM, "map workspace needs %zu bytes, got %zu", need, ws_bytes);
+  mcl_map m = new mcl_map_s();
+  m->W = d->width;
+  m->H = d->height;
+  m->cell = d->cell_m;
+  m->sigma_xy = p->sigma_xy_cells;
+  m->rxy = resolve_radius(p->sigma_xy_cells, p->radius_xy);
+  m->flags = p->flags;
+  m->stream = static_cast<hipStream_t>(stream);
+  carve_map(m, ws, d, p);
+  int64_t nf = 0;
+  for (int64_t i = 0, n = static_cast<int64_t>(m->W) * m->H; i < n; ++i) nf += d->occupancy[i] == 0;
+  m->n_free = nf;
+  double g[kMaxTaps];
+  gaussian_taps(m->sigma_xy, m->rxy, g);
+  hipError_t e = hipMemcpyAsync(m->occ_dev, d->occupancy, static_cast<size_t>(m->W) * m->H,
+                                hipMemcpyHostToDevice, m->stream);
+  if (e == hipSuccess)
+    e = launch_map_setup(m->occ_dev, m->W, m->H, m->pitch, g, m->rxy, 1.0, m->flags, m->free8, m->mpre,
+                         m->wt, m->stream);
+  if (e == hipSuccess && d->range_table) {
+    mcl_status ss = scan_table_build(m->scan, d, m->pitch, m->stream);
+    if (ss != MCL_OK) {
+      delete m;
+      return ss;
+    }
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(m->stream);
+  if (e != hipSuccess) {
+    delete m;
+    return hip_fail(e, "map setup");
+  }
+  *out = m;
+  return MCL_OK;
+}
+
+void mcl_map_destroy(mcl_map m) { delete m; }
+
+size_t mcl_filter_workspace_bytes(mcl_map map, const mcl_params* params) {
+  if (!map || check_params(params, true) != MCL_OK) return 0;
+  return carve_filter(nullptr, nullptr, map, params);
+}
+
+mcl_status mcl_init_belief(mcl_map map, const mcl_params* p, void* ws, size_t ws_bytes, void* stream,
+                           const float* init_host, double theta0, mcl_filter* out) {
+  if (!map || !out) return fail(MCL_EINVAL, "map or out is NULL");
+  mcl_status st = check_params(p, true);
+  if (st != MCL_OK) return st;
+  if (p->sigma_xy_cells != map->sigma_xy || resolve_radius(p->sigma_xy_cells, p->radius_xy) != map->rxy ||
+      p->flags != map->flags)
+    return fail(MCL_EINVAL, "sigma_xy / radius_xy / flags differ from the map's");
+  if (!isfinite(theta0)) return fail(MCL_EINVAL, "theta0 is not finite");
+  if (!ws) return fail(MCL_EINVAL, "workspace is NULL");
+  const size_t need = carve_filter(nullptr, nullptr, map, p);
+  if (ws_bytes < need) return fail(MCL_ENOMEM, "filter workspace needs %zu bytes, got %zu", need, ws_bytes);
+  const int64_t plane = static_cast<int64_t>(map->W) * map->H;
+  if (init_host) {
+    double tot = 0.0;
+    for (int64_t i = 0, n = plane * p->n_theta; i < n; ++i) {
+      const float v = init_host[i];
+      if (!(v >= 0.0f) || !isfinite(v)) return fail(MCL_EINVAL, "init belief has a negative or non-finite value");
+      tot += v;
+    }
+    if (!(tot > 0.0)) return fail(MCL_EINVAL, "init belief has no mass");
+  } else if (map->n_free == 0) {
+    return fail(MCL_EINVAL, "map has no free cell");
+  }
+  mcl_filter f = new mcl_filter_s();
+  f->map = map;
+  f->T = p->n_theta;
+  f->dtype = p->storage;
+  f->sigma_th = p->sigma_theta_bins;
+  f->rth = resolve_radius(p->sigma_theta_bins, p->radius_theta);
+  f->stream = static_cast<hipStream_t>(stream);
+  f->theta = theta0;
+  carve_filter(f, ws, map, p);
+  // taps padded to the kernel radius (zeros beyond each axis' own radius)
+  double g[kMaxTaps];
+  gaussian_taps(map->sigma_xy, map->rxy, g);
+  for (int m = -map->rxy; m <= map->rxy; ++m) f->gxy[f->radius + m] = static_cast<float>(g[m + map->rxy]);
+  gaussian_taps(f->sigma_th, f->rth, g);
+  for (int m = -f->rth; m <= f->rth; ++m) f->gth[f->radius + m] = static_cast<float>(g[m + f->rth]);
+  if (!step_config_supported(f->dtype, f->radius, f->shape.tx, f->shape.ty, f->shape.nt)) {
+    delete f;
+    return fail(MCL_EINVAL, "no kernel for this storage/radius/shape");
+  }
+  hipError_t e = hipSuccess;
+  if (!init_host) {
+    e = launch_init_uniform(f->dtype, f->buf[0], f->buf[1], map->free8, map->W, map->H, map->pitch, f->T,
+                            f->sstride, f->stream);
+    if (e == hipSuccess)
+      e = launch_dev_init(f->dev, static_cast<double>(map->n_free) * f->T, 1.0f, f->stream);
+  } else {
+    const size_t eb = dtype_bytes(f->dtype);
+    e = hipMemsetAsync(f->buf[1], 0, static_cast<size_t>(f->sstride) * f->T * eb, f->stream);
+    for (int k = 0; k < f->T && e == hipSuccess; ++k) {
+      e = hipMemcpyAsync(f->staging, init_host + k * plane, plane * sizeof(float), hipMemcpyHostToDevice,
+                         f->stream);
+      if (e == hipSuccess)
+        e = launch_slice_from_f32(f->dtype, f->staging, static_cast<char*>(f->buf[0]) + k * f->sstride * eb,
+                                  map->W, map->H, map->pitch, f->stream);
+    }
+    if (e == hipSuccess) e = launch_dev_init(f->dev, 1.0, 1.0f, f->stream);
+    if (e == hipSuccess) {
+      ReduceArgs r = make_reduce_args(f, kReduceSet, 1.0);
+      e = launch_reduce(f->dtype, r, kReduceBlocks, f->stream);
+    }
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(f->stream);
+  if (e != hipSuccess) {
+    delete f;
+    return hip_fail(e, "init_belief");
+  }
+  *out = f;
+  return MCL_OK;
+}
+
+void mcl_filter_destroy(mcl_filter f) { delete f; }
+
+mcl_status mcl_step_odometry(mcl_filter f, double u, double v, double w) {
+  if (!f) return fail(MCL_EINVAL, "filter is NULL");
+  if (!isfinite(u) || !isfinite(v) || !isfinite(w)) return fail(MCL_EINVAL, "odometry is not finite");
+  const double cell = f->map->cell;
+  if (fabs(u) / cell > 1e6 || fabs(v) / cell > 1e6) return fail(MCL_EINVAL, "odometry exceeds 1e6 cells");
+  StepArgs a = make_step_args(f);
+  if (f->map->flags & MCL_SUBCELL_GATE) {
+    const double c = cos(f->theta), s = sin(f->theta);
+    const double ax = f->acc_x + u * c - v * s;
+    const double ay = f->acc_y + u * s + v * c;
+    f->theta += w;
+    ++f->steps;
+    if (hypot(ax, ay) < cell) {
+      f->acc_x = ax;
+      f->acc_y = ay;
+      return MCL_OK;
+    }
+    f->acc_x = f->acc_y = 0.0;
+    a.u_cells = ax / cell;
+    a.v_cells = ay / cell;
+    a.theta_prev = 0.0;
+  } else {
+    a.u_cells = u / cell;
+    a.v_cells = v / cell;
+    a.theta_prev = f->theta;
+    f->theta += w;
+    ++f->steps;
+  }
+  HIP_TRY(launch_step(f->dtype, f->radius, f->shape.tx, f->shape.ty, f->shape.nt, a, f->stream), "step launch");
+  return MCL_OK;
+}
+
+mcl_status mcl_normalize(mcl_filter f, double* log_norm_out) {
+  if (!f) return fail(MCL_EINVAL, "filter is NULL");
+  FilterDev d;
+  mcl_status st = read_dev(f, &d);
+  if (st != MCL_OK) return st;
+  if (d.status != kStatusOk) return fail(MCL_EDEGENERATE, "a step removed all probability mass");
+  const double factor = f->dtype == MCL_F16 ? 1.0 / d.maxval : 1.0 / d.sum;
+  ReduceArgs r = make_reduce_args(f, kReduceSet, factor);
+  HIP_TRY(launch_reduce(f->dtype, r, kReduceBlocks, f->stream), "normalize launch");
+  if ((st = read_dev(f, &d)) != MCL_OK) return st;
+  if (log_norm_out) *log_norm_out = d.log_norm;
+  if (d.status != kStatusOk) return fail(MCL_EDEGENERATE, "a step removed all probability mass");
+  return MCL_OK;
+}
+
+mcl_status mcl_export_belief(mcl_filter f, float* dev_out, float* dev_map_out) {
+  if (!f) return fail(MCL_EINVAL, "filter is NULL");
+  if (!dev_out && !dev_map_out) return fail(MCL_EINVAL, "no output given");
+  const mcl_map m = f->map;
+  ReduceArgs r = make_reduce_args(f, kReduceSum, 1.0);
+  HIP_TRY(launch_reduce(f->dtype, r, kReduceBlocks, f->stream), "export sum");
+  // the stored buffer index lives on the device; export reads both through cur
+  FilterDev d;
+  mcl_status st = read_dev(f, &d);
+  if (st != MCL_OK) return st;
+  HIP_TRY(launch_export(f->dtype, f->buf[d.cur], m->W, m->H, m->pitch, f->T, f->sstride, f->dev, dev_out,
+                        static_cast<int64_t>(m->W) * m->H, 0, dev_out ? f->T : 0, dev_map_out, f->stream),
+          "export");
+  return MCL_OK;
+}
+
+mcl_status mcl_read_belief(mcl_filter f, float* host_out, mcl_pose* argmax, double* theta_offset,
+                           double* log_norm) {
+  if (!f) return fail(MCL_EINVAL, "filter is NULL");
+  const mcl_map m = f->map;
+  ReduceArgs r = make_reduce_args(f, kReduceSum, 1.0);
+  HIP_TRY(launch_reduce(f->dtype, r, kReduceBlocks, f->stream), "readout sum");
+  FilterDev d;
+  mcl_status st = read_dev(f, &d);
+  if (st != MCL_OK) return st;
+  const int64_t plane = static_cast<int64_t>(m->W) * m->H;
+  if (host_out) {
+    for (int k = 0; k < f->T; ++k) {
+      HIP_TRY(launch_export(f->dtype, f->buf[d.cur], m->W, m->H, m->pitch, f->T, f->sstride, f->dev,
+                            f->staging, plane, k, k + 1, nullptr, f->stream),
+              "export slice");
+      HIP_TRY(hipMemcpyAsync(host_out + k * plane, f->staging, plane * sizeof(float), hipMemcpyDeviceToHost,
+                             f->stream),
+              "copy slice");
+    }
+  }
+  if (argmax) {
+    ReduceArgs ra = make_reduce_args(f, kReduceArgmax, 1.0);
+    HIP_TRY(launch_reduce(f->dtype, ra, kReduceBlocks, f->stream), "argmax");
+  }
+  if ((st = read_dev(f, &d)) != MCL_OK) return st;
+  if (argmax) {
+    const int64_t idx = d.argmax_idx < 0 ? 0 : d.argmax_idx;
+    argmax->k = static_cast<int32_t>(idx / plane);
+    const int64_t rem = idx % plane;
+    argmax->j = static_cast<int32_t>(rem / m->W);
+    argmax->i = static_cast<int32_t>(rem % m->W);
+    argmax->x_m = argmax->i * m->cell;
+    argmax->y_m = argmax->j * m->cell;
+    argmax->theta_rad = argmax->k * (2.0 * M_PI / f->T) + f->theta;
+    argmax->prob = static_cast<double>(d.argmax_val) / d.aux[3];
+  }
+  if (theta_offset) *theta_offset = f->theta;
+  if (log_norm) *log_norm = d.log_norm;
+  if (d.status != kStatusOk) return fail(MCL_EDEGENERATE, "a step removed all probability mass");
+  return MCL_OK;
+}
+
+mcl_status mcl_get_info(mcl_filter f, int sync, mcl_info* out) {
+  if (!f || !out) return fail(MCL_EINVAL, "filter or out is NULL");
+  memset(out, 0, sizeof(*out));
+  out->width = f->map->W;
+  out->height = f->map->H;
+  out->n_theta = f->T;
+  out->pitch = f->map->pitch;
+  out->storage = f->dtype;
+  out->radius = f->radius;
+  out->tile_x = f->shape.tx;
+  out->tile_y = f->shape.ty;
+  out->theta_chunks = f->shape.chunks;
+  out->workgroups = f->shape.blocks();
+  out->steps = f->steps;
+  out->theta_offset_rad = f->theta;
+  out->state_bytes = static_cast<uint64_t>(f->map->W) * f->map->H * f->T * dtype_bytes(f->dtype);
+  if (sync) {
+    FilterDev d;
+    mcl_status st = read_dev(f, &d);
+    if (st != MCL_OK) return st;
+    out->log_norm = d.log_norm;
+    out->status = d.status;
+    out->belief_device = f->buf[d.cur];
+  } else {
+    out->belief_device = nullptr;
+  }
+  return MCL_OK;
+}
+
+mcl_status mcl_apply_scan(mcl_filter f, const float* ranges_m, int32_t n_beams, double sigma_m) {
+  if (!f) return fail(MCL_EINVAL, "filter is NULL");
+  return scan_apply(f, ranges_m, n_beams, sigma_m);
+}
+
+mcl_status mcl_scan_sqdist(mcl_filter f, const float* ranges_m, int32_t n_beams, int32_t* dev_out) {
+  if (!f) return fail(MCL_EINVAL, "filter is NULL");
+  return scan_sqdist(f, ranges_m, n_beams, dev_out);
+}
+
+mcl_status mcl_step_batch(mcl_filter* const filters, const double* uvw, int32_t n, void* stream) {
+  (void)filters;
+  (void)uvw;
+  (void)n;
+  (void)stream;
+  return fail(MCL_ESTATE, "step_batch is not available in this build");
+}
+
+}  // extern "C"

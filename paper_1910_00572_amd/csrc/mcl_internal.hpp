@@ -1,0 +1,106 @@
+// Internal definitions shared by the host library and the HIP kernels.
+// Nothing here is part of the public ABI (include/mcl.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mcl {
+
+constexpr int kMaxRadius = 4;                 // largest blur radius the kernels support
+constexpr int kMaxTaps = 2 * kMaxRadius + 1;
+constexpr int kMaxTheta = 360;                // heading channels per filter
+constexpr int kRowAlign = 8;                  // row pitch multiple (16 bytes of 16-bit storage)
+constexpr int kStatusOk = 0;
+constexpr int kStatusDegenerate = 3;
+
+// Device-resident scalars of one filter.  Written only by the last workgroup of
+// a launch (or by setup kernels), read by the next launch on the same stream.
+struct FilterDev {
+  double log_norm;     // ln of the product of kept masses since initialisation
+  double lnsum;        // ln(sum of the stored buffer)
+  double sum;          // sum of the stored buffer
+  double aux[4];       // scan: [0] = M*, [1] = ln(stored value at the best state), [2] = D at it
+  float scale;         // factor the next update applies on load (1 / max of the stored buffer)
+  float maxval;        // max of the stored buffer
+  int32_t cur;         // which of the two belief buffers holds the state
+  int32_t status;      // sticky: kStatusOk or kStatusDegenerate
+  uint32_t counter;    // arrival counter of the last-workgroup reduction
+  uint32_t pad0;
+  int64_t argmax_idx;  // flat (k, j, i) index of the readout argmax
+  float argmax_val;
+  float pad1;
+};
+
+// Everything one step of one filter needs.  Passed by value for a single
+// filter, or from device memory for a batch.
+struct StepArgs {
+  void* buf[2];               // belief buffers, storage type, [k][j][pitch]
+  const float* mpre;          // pre-blur traversability, [j][pitch] (0 outside the grid)
+  const float* wt;            // post-blur weights M / G(B_0), [j][pitch]
+  double* partials;           // 2 doubles per workgroup
+  FilterDev* dev;
+  int32_t W, H, pitch, n_theta;
+  int32_t tiles_x, tiles_y, chunks, chunk_len;
+  int64_t sstride;            // elements per heading slice (H * pitch)
+  double u_cells, v_cells;    // odometry in cells, robot frame
+  double theta_prev, dtheta;  // heading offset before the step, 2 pi / n_theta
+  float gxy[kMaxTaps];        // x/y taps, centred at index R of the kernel radius
+  float gth[kMaxTaps];        // theta taps
+};
+
+// Gaussian taps of the map's x/y blur (FP64, index m + radius).
+struct MapTaps {
+  double g[kMaxTaps];
+};
+
+// Generic pass over a stored belief with a last-workgroup reduction.
+struct ReduceArgs {
+  void* buf[2];
+  double* partials;
+  FilterDev* dev;
+  int32_t W, H, pitch, n_theta;
+  int64_t sstride;
+  double factor;              // multiply the stored buffer in place by this (1 = read only)
+  int32_t mode;               // kReduceSet / kReduceArgmax
+};
+constexpr int kReduceSet = 0;     // sum/max -> dev (sum, lnsum, scale, maxval)
+constexpr int kReduceArgmax = 1;  // argmax -> dev (argmax_idx, argmax_val)
+constexpr int kReduceSum = 2;     // sum -> dev->aux[3] only (export normaliser)
+
+// Bump allocator over a caller-provided buffer; with base == nullptr it only
+// measures.  Every region starts on a 256-byte boundary.
+struct Carver {
+  char* base;
+  size_t off = 0;
+  explicit Carver(void* b) : base(static_cast<char*>(b)) {}
+  void* take(size_t bytes) {
+    off = (off + 255) & ~static_cast<size_t>(255);
+    void* p = base ? base + off : nullptr;
+    off += bytes;
+    return p;
+  }
+};
+
+// ---- launchers (defined in the .hip files) -----------------------------------
+// Return hipSuccess or the launch error.
+hipError_t launch_step(int dtype, int radius, int tx, int ty, int nt, const StepArgs& a,
+                       hipStream_t s);
+hipError_t launch_step_batch(int dtype, int radius, int tx, int ty, int nt, const StepArgs* jobs_dev,
+                             const int32_t* block_job_dev, int32_t total_blocks, hipStream_t s);
+bool step_config_supported(int dtype, int radius, int tx, int ty, int nt);
+
+hipError_t launch_map_setup(const uint8_t* occ_dev, int W, int H, int pitch, const double* gxy,
+                            int rxy, double gth_sum, uint32_t flags, uint8_t* free8, float* mpre,
+                            float* wt, hipStream_t s);
+hipError_t launch_init_uniform(int dtype, void* buf0, void* buf1, const uint8_t* free8, int W, int H,
+                               int pitch, int n_theta, int64_t sstride, hipStream_t s);
+hipError_t launch_slice_from_f32(int dtype, const float* src, void* dst_slice, int W, int H,
+                                 int pitch, hipStream_t s);
+hipError_t launch_reduce(int dtype, const ReduceArgs& a, int nblocks, hipStream_t s);
+hipError_t launch_export(int dtype, const void* buf, int W, int H, int pitch, int n_theta,
+                         int64_t sstride, const FilterDev* dev, float* out, int64_t out_slice_stride,
+                         int k_begin, int k_end, float* map_out, hipStream_t s);
+hipError_t launch_dev_init(FilterDev* dev, double sum, float maxval, hipStream_t s);
+
+}  // namespace mcl

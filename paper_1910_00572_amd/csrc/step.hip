@@ -1,0 +1,514 @@
+// Fused odometry step of the belief-tensor filter for gfx950.
+//
+// One launch applies Alg. 1 to the whole tensor and renormalises:
+//   S  = M_pre (.) warp_k(s * B_k)            bilinear per-channel shift (Sec. III-A-1)
+//   T  = g_theta *_theta g_y *_y g_x *_x S    separable Gaussian (Sec. III-A-2)
+//   B' = W_post (.) T                         W_post = M / G(B_0)   (Sec. III-A-3)
+// followed by the sum / max reduction that renormalises the belief (the eta
+// of eq. sensor update, applied after every step) and a lazily applied scale
+// s = 1 / max that keeps 16-bit storage in range.
+//
+// Design (2.5-D stencil): a workgroup owns an output tile of TX x TY cells
+// and streams through the heading channels.  For every channel it
+//   P1  stages the shifted source window (TY+2R+1 rows) from HBM into LDS,
+//       realigned so the fractional shift reads aligned 16-byte words;
+//   P2  applies the bilinear weights and the pre-blur mask -> S in LDS;
+//   P3  blurs along y -> LDS;   P4  blurs along x -> registers;
+//   P5  keeps the last 2R+1 channels in a register ring and emits the
+//       theta-blurred, masked, wall-normalised output of channel j-R.
+// The next channel's window is loaded into registers while P2-P4 run.  Each
+// state is read from HBM once (plus the halo, shared through L2) and written
+// once.  The circular theta blur starts R channels early and runs R late,
+// wrapping the channel index.  The sum/max reduction is finished by the last
+// workgroup to arrive (atomic counter), so a step is a single launch whose
+// result does not depend on workgroup timing.
+#include <float.h>
+#include <math.h>
+
+#include "mcl_internal.hpp"
+
+namespace mcl {
+namespace {
+
+// ---- storage types -------------------------------------------------------------
+template <typename T>
+struct Store;
+
+template <>
+struct Store<float> {
+  static constexpr int VEC = 4;  // elements per 16-byte word
+  __device__ static inline void unpack(const uint4& r, float* o) {
+    o[0] = __uint_as_float(r.x);
+    o[1] = __uint_as_float(r.y);
+    o[2] = __uint_as_float(r.z);
+    o[3] = __uint_as_float(r.w);
+  }
+  __device__ static inline void store4(float* p, const float* v) {
+    *reinterpret_cast<float4*>(p) = make_float4(v[0], v[1], v[2], v[3]);
+  }
+};
+
+template <>
+struct Store<__bf16> {
+  static constexpr int VEC = 8;
+  __device__ static inline void unpack(const uint4& r, float* o) {
+    const uint32_t w[4] = {r.x, r.y, r.z, r.w};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      o[2 * i] = __uint_as_float(w[i] << 16);
+      o[2 * i + 1] = __uint_as_float(w[i] & 0xffff0000u);
+    }
+  }
+  __device__ static inline uint32_t pack2(float a, float b) {
+    const uint32_t lo = __builtin_bit_cast(uint16_t, static_cast<__bf16>(a));
+    const uint32_t hi = __builtin_bit_cast(uint16_t, static_cast<__bf16>(b));
+    return lo | (hi << 16);
+  }
+  __device__ static inline void store4(__bf16* p, const float* v) {
+    *reinterpret_cast<uint2*>(p) = make_uint2(pack2(v[0], v[1]), pack2(v[2], v[3]));
+  }
+};
+
+template <>
+struct Store<_Float16> {
+  static constexpr int VEC = 8;
+  __device__ static inline void unpack(const uint4& r, float* o) {
+    const uint32_t w[4] = {r.x, r.y, r.z, r.w};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      o[2 * i] = static_cast<float>(__builtin_bit_cast(_Float16, static_cast<uint16_t>(w[i] & 0xffffu)));
+      o[2 * i + 1] = static_cast<float>(__builtin_bit_cast(_Float16, static_cast<uint16_t>(w[i] >> 16)));
+    }
+  }
+  __device__ static inline uint32_t pack2(float a, float b) {
+    const uint32_t lo = __builtin_bit_cast(uint16_t, static_cast<_Float16>(a));
+    const uint32_t hi = __builtin_bit_cast(uint16_t, static_cast<_Float16>(b));
+    return lo | (hi << 16);
+  }
+  __device__ static inline void store4(_Float16* p, const float* v) {
+    *reinterpret_cast<uint2*>(p) = make_uint2(pack2(v[0], v[1]), pack2(v[2], v[3]));
+  }
+};
+
+// Spread consecutive workgroups over the 8 XCDs so that each XCD (own L2)
+// receives a contiguous band of tiles: neighbouring tiles share halo rows.
+__device__ inline int xcd_remap(int b, int n) {
+  constexpr int X = 8;
+  const int q = n / X, r = n % X;
+  const int x = b % X, i = b / X;
+  return (x < r) ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
+}
+
+template <typename T, int R, int TX, int TY, int NT>
+__device__ __forceinline__ void step_body(const StepArgs& a, const int blk, const int nblk) {
+  constexpr int VEC = Store<T>::VEC;
+  constexpr int RQ = 4;                      // x halo of the S/Y region, one quad
+  constexpr int SC = TX + 2 * RQ;            // S/Y region width
+  constexpr int SCP = SC + 4;                // LDS row pitch (floats)
+  constexpr int SR = TY + 2 * R;             // S rows
+  constexpr int WR = SR + 1;                 // source-window rows
+  constexpr int NV = (SC + VEC) / VEC;       // 16-byte words per window row
+  constexpr int NRAW = WR * NV;
+  constexpr int IPT1 = (NRAW + NT - 1) / NT;
+  constexpr int NQ = SC / 4;                 // quads per S/Y row
+  constexpr int NS = (SR / 2) * NQ;          // P2 items: 2 rows x 1 quad
+  constexpr int IPT2 = (NS + NT - 1) / NT;
+  constexpr int NYI = (TY / 2) * NQ;         // P3 items: 2 rows x 1 quad
+  constexpr int IPT3 = (NYI + NT - 1) / NT;
+  constexpr int OQ = TX / 4;
+  constexpr int NP = TY * OQ;                // P4 items: 1 row x 1 quad
+  constexpr int IPT4 = NP / NT;
+  constexpr int RING = 2 * R + 1;
+  static_assert(NP % NT == 0, "output quads must divide evenly");
+  static_assert(SC % VEC == 0 && TY % 2 == 0, "tile shape");
+  static_assert(R >= 1 && R <= kMaxRadius, "radius");
+  static_assert((NT & (NT - 1)) == 0, "power-of-two workgroup");
+
+  __shared__ __attribute__((aligned(16))) float rawL[WR][SCP];
+  __shared__ __attribute__((aligned(16))) float sL[SR][SCP];
+  __shared__ __attribute__((aligned(16))) float yL[TY][SCP];
+  __shared__ int pnx[kMaxTheta], pny[kMaxTheta];
+  __shared__ float pfx[kMaxTheta], pfy[kMaxTheta];
+  __shared__ double red_s[NT];
+  __shared__ float red_m[NT];
+  __shared__ int last_flag;
+
+  const int t = threadIdx.x;
+  const int W = a.W, H = a.H, pitch = a.pitch, nth = a.n_theta;
+  (void)W;
+  const int64_t sstride = a.sstride;
+  const int tiles_x = a.tiles_x;
+  const int ntile = tiles_x * a.tiles_y;
+  const int chunk = blk / ntile, tile = blk % ntile;
+  const int x0 = (tile % tiles_x) * TX;
+  const int y0 = (tile / tiles_x) * TY;
+  const int kbeg = chunk * a.chunk_len;
+  const int kend = min(nth, kbeg + a.chunk_len);
+  FilterDev* dev = a.dev;
+  const int cur = dev->cur;
+  const float scale = dev->scale;
+  const T* __restrict__ bin = static_cast<const T*>(a.buf[cur]);
+  T* __restrict__ bout = static_cast<T*>(a.buf[cur ^ 1]);
+  const double u = a.u_cells, v = a.v_cells, th0 = a.theta_prev, dth = a.dtheta;
+
+  // Per-channel displacement R(theta + k dtheta) [u, v] in cells, split into
+  // integer and fractional parts (FP64, once per workgroup).
+  for (int k = t; k < nth; k += NT) {
+    double sn, cs;
+    sincos(th0 + k * dth, &sn, &cs);
+    const double dx = u * cs - v * sn;
+    const double dy = u * sn + v * cs;
+    const double fdx = floor(dx), fdy = floor(dy);
+    pnx[k] = static_cast<int>(fdx);
+    pny[k] = static_cast<int>(fdy);
+    pfx[k] = static_cast<float>(dx - fdx);
+    pfy[k] = static_cast<float>(dy - fdy);
+  }
+  float gx[RING], gt[RING];
+#pragma unroll
+  for (int l = 0; l < RING; ++l) {
+    gx[l] = a.gxy[l];
+    gt[l] = a.gth[l];
+  }
+
+  // Pre-blur mask of this thread's P2 items, wall weights of its outputs.
+  float mreg[IPT2][2][4];
+#pragma unroll
+  for (int i = 0; i < IPT2; ++i) {
+    const int id = t + i * NT;
+    const int srp = id / NQ, q = id % NQ;
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      const int y = y0 - R + 2 * srp + s;
+      const int x = x0 - RQ + 4 * q;
+      float4 mv = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (id < NS && y >= 0 && y < H && x >= 0 && x < pitch)
+        mv = *reinterpret_cast<const float4*>(a.mpre + static_cast<int64_t>(y) * pitch + x);
+      mreg[i][s][0] = mv.x;
+      mreg[i][s][1] = mv.y;
+      mreg[i][s][2] = mv.z;
+      mreg[i][s][3] = mv.w;
+    }
+  }
+  float wreg[IPT4][4];
+  int64_t ooff[IPT4];
+  bool ostore[IPT4];
+#pragma unroll
+  for (int i = 0; i < IPT4; ++i) {
+    const int id = t + i * NT;
+    const int yr = id / OQ, oq = id % OQ;
+    const int y = y0 + yr, x = x0 + 4 * oq;
+    ostore[i] = (y < H) && (x < pitch);
+    ooff[i] = static_cast<int64_t>(y) * pitch + x;
+    float4 wv = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (ostore[i]) wv = *reinterpret_cast<const float4*>(a.wt + ooff[i]);
+    wreg[i][0] = wv.x * scale;
+    wreg[i][1] = wv.y * scale;
+    wreg[i][2] = wv.z * scale;
+    wreg[i][3] = wv.w * scale;
+  }
+
+  float ring[IPT4][RING][4];
+  float psum = 0.f, pmax = 0.f;
+  const int jbeg = kbeg - R;
+  const int count = (kend - kbeg) + 2 * R;
+
+  auto phys = [nth](int j) {
+    int k = j % nth;
+    return k < 0 ? k + nth : k;
+  };
+
+  uint4 pre[IPT1];
+  auto issue_loads = [&](int j) {
+    const int kp = phys(j);
+    const int colbase = x0 - RQ - pnx[kp] - 1;
+    const int xa = colbase - (((colbase % VEC) + VEC) % VEC);
+    const int rowbase = y0 - R - pny[kp] - 1;
+    const T* base = bin + static_cast<int64_t>(kp) * sstride;
+#pragma unroll
+    for (int i = 0; i < IPT1; ++i) {
+      const int id = t + i * NT;
+      const int r = id / NV, vv = id % NV;
+      const int gy = rowbase + r;
+      const int gxe = xa + vv * VEC;
+      pre[i] = make_uint4(0u, 0u, 0u, 0u);
+      if (id < NRAW && static_cast<unsigned>(gy) < static_cast<unsigned>(H) && gxe >= 0 && gxe < pitch)
+        pre[i] = *reinterpret_cast<const uint4*>(base + static_cast<int64_t>(gy) * pitch + gxe);
+    }
+  };
+
+  __syncthreads();  // shift table ready
+  issue_loads(jbeg);
+
+  for (int jj = 0; jj < count; jj += RING) {
+#pragma unroll
+    for (int p = 0; p < RING; ++p) {
+      const int jrel = jj + p;
+      if (jrel < count) {
+        const int j = jbeg + jrel;
+        const int kp = phys(j);
+        const float fx = pfx[kp], fy = pfy[kp];
+        {
+          // P1: window registers -> LDS, realigned by m so that S column c
+          // reads window columns c (weight fx) and c+1 (weight 1-fx).
+          const int colbase = x0 - RQ - pnx[kp] - 1;
+          const int m = ((colbase % VEC) + VEC) % VEC;
+#pragma unroll
+          for (int i = 0; i < IPT1; ++i) {
+            const int id = t + i * NT;
+            if (id < NRAW) {
+              const int r = id / NV, vv = id % NV;
+              float vals[VEC];
+              Store<T>::unpack(pre[i], vals);
+#pragma unroll
+              for (int e = 0; e < VEC; ++e) {
+                const int c = vv * VEC + e - m;
+                if (c >= 0 && c <= SC) rawL[r][c] = vals[e];
+              }
+            }
+          }
+        }
+        __syncthreads();
+        if (jrel + 1 < count) issue_loads(j + 1);
+
+        // P2: bilinear weights and pre-blur mask -> S.
+#pragma unroll
+        for (int i = 0; i < IPT2; ++i) {
+          const int id = t + i * NT;
+          if (id < NS) {
+            const int srp = id / NQ, q = id % NQ;
+            float xr[3][4];
+#pragma unroll
+            for (int rr = 0; rr < 3; ++rr) {
+              const float4 w4 = *reinterpret_cast<const float4*>(&rawL[2 * srp + rr][4 * q]);
+              const float w5 = rawL[2 * srp + rr][4 * q + 4];
+              const float wv[5] = {w4.x, w4.y, w4.z, w4.w, w5};
+#pragma unroll
+              for (int e = 0; e < 4; ++e) xr[rr][e] = fmaf(fx, wv[e] - wv[e + 1], wv[e + 1]);
+            }
+#pragma unroll
+            for (int s = 0; s < 2; ++s) {
+              float sv[4];
+#pragma unroll
+              for (int e = 0; e < 4; ++e)
+                sv[e] = fmaf(fy, xr[s][e] - xr[s + 1][e], xr[s + 1][e]) * mreg[i][s][e];
+              *reinterpret_cast<float4*>(&sL[2 * srp + s][4 * q]) = make_float4(sv[0], sv[1], sv[2], sv[3]);
+            }
+          }
+        }
+        __syncthreads();
+
+        // P3: blur along y, two output rows per item.
+#pragma unroll
+        for (int i = 0; i < IPT3; ++i) {
+          const int id = t + i * NT;
+          if (id < NYI) {
+            const int yrp = id / NQ, q = id % NQ;
+            float a0[4] = {0.f, 0.f, 0.f, 0.f}, a1[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int l = 0; l <= 2 * R + 1; ++l) {
+              const float4 s4 = *reinterpret_cast<const float4*>(&sL[2 * yrp + l][4 * q]);
+              const float sv[4] = {s4.x, s4.y, s4.z, s4.w};
+#pragma unroll
+              for (int e = 0; e < 4; ++e) {
+                if (l <= 2 * R) a0[e] = fmaf(gx[l], sv[e], a0[e]);
+                if (l >= 1) a1[e] = fmaf(gx[l - 1], sv[e], a1[e]);
+              }
+            }
+            *reinterpret_cast<float4*>(&yL[2 * yrp][4 * q]) = make_float4(a0[0], a0[1], a0[2], a0[3]);
+            *reinterpret_cast<float4*>(&yL[2 * yrp + 1][4 * q]) = make_float4(a1[0], a1[1], a1[2], a1[3]);
+          }
+        }
+        __syncthreads();
+
+        // P4: blur along x into the ring slot of this channel.
+#pragma unroll
+        for (int i = 0; i < IPT4; ++i) {
+          const int id = t + i * NT;
+          const int yr = id / OQ, oq = id % OQ;
+          float yv[12];
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            const float4 y4 = *reinterpret_cast<const float4*>(&yL[yr][4 * oq + 4 * c]);
+            yv[4 * c] = y4.x;
+            yv[4 * c + 1] = y4.y;
+            yv[4 * c + 2] = y4.z;
+            yv[4 * c + 3] = y4.w;
+          }
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            float acc = 0.f;
+#pragma unroll
+            for (int l = 0; l < RING; ++l) acc = fmaf(gx[l], yv[RQ - R + e + l], acc);
+            ring[i][p][e] = acc;
+          }
+        }
+
+        // P5: theta blur of channel j - R, post-blur weights, store, reduce.
+        if (jrel >= 2 * R) {
+          const int ko = phys(j - R);
+          T* obase = bout + static_cast<int64_t>(ko) * sstride;
+#pragma unroll
+          for (int i = 0; i < IPT4; ++i) {
+            float o[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+              float acc = 0.f;
+#pragma unroll
+              for (int l = 0; l < RING; ++l) acc = fmaf(gt[l], ring[i][(p - 2 * R + l + RING) % RING][e], acc);
+              o[e] = acc * wreg[i][e];
+              psum += o[e];
+              pmax = fmaxf(pmax, o[e]);
+            }
+            if (ostore[i]) Store<T>::store4(obase + ooff[i], o);
+          }
+        }
+      }
+    }
+  }
+
+  // Workgroup partial (fixed tree), then the last workgroup to arrive
+  // reduces all partials in a fixed order and updates the filter scalars.
+  red_s[t] = static_cast<double>(psum);
+  red_m[t] = pmax;
+  __syncthreads();
+#pragma unroll
+  for (int s = NT / 2; s > 0; s >>= 1) {
+    if (t < s) {
+      red_s[t] += red_s[t + s];
+      red_m[t] = fmaxf(red_m[t], red_m[t + s]);
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    a.partials[2 * blk] = red_s[0];
+    a.partials[2 * blk + 1] = static_cast<double>(red_m[0]);
+    const uint32_t prev = __hip_atomic_fetch_add(&dev->counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    last_flag = (prev == static_cast<uint32_t>(nblk - 1));
+  }
+  __syncthreads();
+  if (!last_flag) return;
+
+  double s = 0.0;
+  float mx = 0.f;
+  for (int b = t; b < nblk; b += NT) {
+    s += __hip_atomic_load(&a.partials[2 * b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    mx = fmaxf(mx, static_cast<float>(__hip_atomic_load(&a.partials[2 * b + 1], __ATOMIC_RELAXED,
+                                                        __HIP_MEMORY_SCOPE_AGENT)));
+  }
+  red_s[t] = s;
+  red_m[t] = mx;
+  __syncthreads();
+#pragma unroll
+  for (int st = NT / 2; st > 0; st >>= 1) {
+    if (t < st) {
+      red_s[t] += red_s[t + st];
+      red_m[t] = fmaxf(red_m[t], red_m[t + st]);
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    const double tot = red_s[0];
+    const float m = red_m[0];
+    if (!(tot > 0.0) || !isfinite(tot) || !(m > 0.f)) {
+      dev->status = kStatusDegenerate;  // keep the previous belief (cur unchanged)
+    } else {
+      dev->log_norm += log(tot) - log(static_cast<double>(scale)) - dev->lnsum;
+      dev->lnsum = log(tot);
+      dev->sum = tot;
+      dev->maxval = m;
+      const double sc = 1.0 / static_cast<double>(m);
+      dev->scale = sc > static_cast<double>(FLT_MAX) ? FLT_MAX : static_cast<float>(sc);
+      dev->cur = cur ^ 1;
+    }
+    __hip_atomic_store(&dev->counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+template <typename T, int R, int TX, int TY, int NT>
+__global__ __launch_bounds__(NT) void step_single(StepArgs a) {
+  const int n = a.tiles_x * a.tiles_y * a.chunks;
+  step_body<T, R, TX, TY, NT>(a, xcd_remap(blockIdx.x, n), n);
+}
+
+// Batch: block_job[2*g] = job, block_job[2*g+1] = block within that job.
+template <typename T, int R, int TX, int TY, int NT>
+__global__ __launch_bounds__(NT) void step_batch(const StepArgs* __restrict__ jobs,
+                                                 const int32_t* __restrict__ block_job, int total) {
+  const int g = xcd_remap(blockIdx.x, total);
+  const StepArgs& a = jobs[block_job[2 * g]];
+  const int n = a.tiles_x * a.tiles_y * a.chunks;
+  step_body<T, R, TX, TY, NT>(a, block_job[2 * g + 1], n);
+}
+
+template <typename T, int R, int TX, int TY, int NT>
+hipError_t launch_one(const StepArgs& a, hipStream_t s) {
+  const int n = a.tiles_x * a.tiles_y * a.chunks;
+  hipLaunchKernelGGL((step_single<T, R, TX, TY, NT>), dim3(n), dim3(NT), 0, s, a);
+  return hipGetLastError();
+}
+
+template <typename T, int R, int TX, int TY, int NT>
+hipError_t launch_many(const StepArgs* jobs, const int32_t* bj, int total, hipStream_t s) {
+  hipLaunchKernelGGL((step_batch<T, R, TX, TY, NT>), dim3(total), dim3(NT), 0, s, jobs, bj, total);
+  return hipGetLastError();
+}
+
+// Instantiated launch shapes: (TX, TY, NT).
+#define MCL_SHAPES(X) X(64, 16, 256) X(32, 16, 128)
+
+template <typename T, int R>
+hipError_t dispatch_shape(int tx, int ty, int nt, const StepArgs* single, const StepArgs* jobs,
+                          const int32_t* bj, int total, hipStream_t s) {
+#define MCL_TRY(TX_, TY_, NT_)                                                  \
+  if (tx == TX_ && ty == TY_ && nt == NT_)                                      \
+    return single ? launch_one<T, R, TX_, TY_, NT_>(*single, s)                 \
+                  : launch_many<T, R, TX_, TY_, NT_>(jobs, bj, total, s);
+  MCL_SHAPES(MCL_TRY)
+#undef MCL_TRY
+  return hipErrorInvalidValue;
+}
+
+template <typename T>
+hipError_t dispatch_radius(int radius, int tx, int ty, int nt, const StepArgs* single,
+                           const StepArgs* jobs, const int32_t* bj, int total, hipStream_t s) {
+  switch (radius) {
+    case 1: return dispatch_shape<T, 1>(tx, ty, nt, single, jobs, bj, total, s);
+    case 2: return dispatch_shape<T, 2>(tx, ty, nt, single, jobs, bj, total, s);
+    case 3: return dispatch_shape<T, 3>(tx, ty, nt, single, jobs, bj, total, s);
+    case 4: return dispatch_shape<T, 4>(tx, ty, nt, single, jobs, bj, total, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t dispatch(int dtype, int radius, int tx, int ty, int nt, const StepArgs* single,
+                    const StepArgs* jobs, const int32_t* bj, int total, hipStream_t s) {
+  switch (dtype) {
+    case 0: return dispatch_radius<float>(radius, tx, ty, nt, single, jobs, bj, total, s);
+    case 1: return dispatch_radius<__bf16>(radius, tx, ty, nt, single, jobs, bj, total, s);
+    case 2: return dispatch_radius<_Float16>(radius, tx, ty, nt, single, jobs, bj, total, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace
+
+bool step_config_supported(int dtype, int radius, int tx, int ty, int nt) {
+  if (dtype < 0 || dtype > 2 || radius < 1 || radius > kMaxRadius) return false;
+#define MCL_HAS(TX_, TY_, NT_) \
+  if (tx == TX_ && ty == TY_ && nt == NT_) return true;
+  MCL_SHAPES(MCL_HAS)
+#undef MCL_HAS
+  return false;
+}
+
+hipError_t launch_step(int dtype, int radius, int tx, int ty, int nt, const StepArgs& a, hipStream_t s) {
+  return dispatch(dtype, radius, tx, ty, nt, &a, nullptr, nullptr, 0, s);
+}
+
+hipError_t launch_step_batch(int dtype, int radius, int tx, int ty, int nt, const StepArgs* jobs_dev,
+                             const int32_t* block_job_dev, int32_t total_blocks, hipStream_t s) {
+  return dispatch(dtype, radius, tx, ty, nt, nullptr, jobs_dev, block_job_dev, total_blocks, s);
+}
+
+}  // namespace mcl

@@ -1,0 +1,282 @@
+"""Python binding of the C ABI in include/mcl.h (argument marshalling only).
+
+Every computation runs in libmcl.so's HIP kernels.  PyTorch supplies device
+memory (the workspaces are torch uint8 tensors) and the current HIP stream.
+Importing this module fails loudly when libmcl.so has not been built.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, byref, c_double, c_int, c_int32, c_int64, c_size_t, c_uint32, c_uint64, c_void_p
+
+import numpy as np
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libmcl.so")
+
+F32, BF16, F16 = 0, 1, 2
+DTYPES = {"f32": F32, "bf16": BF16, "f16": F16}
+MASK_BEFORE_BLUR, WALL_NORMALIZE, SUBCELL_GATE, SCAN_F32 = 1, 2, 4, 8
+DEFAULT_FLAGS = MASK_BEFORE_BLUR | WALL_NORMALIZE
+OK, EINVAL, ENOMEM, EDEGENERATE, EDEVICE, ESTATE = range(6)
+STATUS_NAMES = {0: "MCL_OK", 1: "MCL_EINVAL", 2: "MCL_ENOMEM", 3: "MCL_EDEGENERATE",
+                4: "MCL_EDEVICE", 5: "MCL_ESTATE"}
+
+# Every symbol include/mcl.h declares.
+ABI_SYMBOLS = [
+    "mcl_last_error", "mcl_map_workspace_bytes", "mcl_map_create", "mcl_map_destroy",
+    "mcl_filter_workspace_bytes", "mcl_init_belief", "mcl_filter_destroy", "mcl_step_odometry",
+    "mcl_apply_scan", "mcl_normalize", "mcl_read_belief", "mcl_export_belief", "mcl_scan_sqdist",
+    "mcl_get_info", "mcl_step_batch",
+]
+
+
+class MapDesc(ctypes.Structure):
+    _fields_ = [("width", c_int32), ("height", c_int32), ("cell_m", c_double),
+                ("occupancy", c_void_p), ("range_table", c_void_p), ("n_dirs", c_int32),
+                ("max_range_m", c_double)]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("n_theta", c_int32), ("sigma_xy_cells", c_double), ("sigma_theta_bins", c_double),
+                ("radius_xy", c_int32), ("radius_theta", c_int32), ("storage", c_int32),
+                ("flags", c_uint32)]
+
+
+class Pose(ctypes.Structure):
+    _fields_ = [("i", c_int32), ("j", c_int32), ("k", c_int32), ("x_m", c_double), ("y_m", c_double),
+                ("theta_rad", c_double), ("prob", c_double)]
+
+    def as_tuple(self):
+        return (self.k, self.j, self.i)
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("width", c_int32), ("height", c_int32), ("n_theta", c_int32), ("pitch", c_int32),
+                ("storage", c_int32), ("radius", c_int32), ("tile_x", c_int32), ("tile_y", c_int32),
+                ("theta_chunks", c_int32), ("workgroups", c_int32), ("steps", c_int64),
+                ("theta_offset_rad", c_double), ("log_norm", c_double), ("status", c_int32),
+                ("belief_device", c_void_p), ("state_bytes", c_uint64)]
+
+
+class MclError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+_lib = None
+
+
+def load_library(path: str = _LIB_PATH):
+    """Load libmcl.so (raises if it is missing) and declare the ABI signatures."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with `python -m paper_1910_00572_amd.build`")
+    lib = ctypes.CDLL(path)
+    lib.mcl_last_error.restype = ctypes.c_char_p
+    lib.mcl_last_error.argtypes = []
+    lib.mcl_map_workspace_bytes.restype = c_size_t
+    lib.mcl_map_workspace_bytes.argtypes = [POINTER(MapDesc), POINTER(Params)]
+    lib.mcl_map_create.restype = c_int
+    lib.mcl_map_create.argtypes = [POINTER(MapDesc), POINTER(Params), c_void_p, c_size_t, c_void_p,
+                                   POINTER(c_void_p)]
+    lib.mcl_map_destroy.restype = None
+    lib.mcl_map_destroy.argtypes = [c_void_p]
+    lib.mcl_filter_workspace_bytes.restype = c_size_t
+    lib.mcl_filter_workspace_bytes.argtypes = [c_void_p, POINTER(Params)]
+    lib.mcl_init_belief.restype = c_int
+    lib.mcl_init_belief.argtypes = [c_void_p, POINTER(Params), c_void_p, c_size_t, c_void_p, c_void_p,
+                                    c_double, POINTER(c_void_p)]
+    lib.mcl_filter_destroy.restype = None
+    lib.mcl_filter_destroy.argtypes = [c_void_p]
+    lib.mcl_step_odometry.restype = c_int
+    lib.mcl_step_odometry.argtypes = [c_void_p, c_double, c_double, c_double]
+    lib.mcl_apply_scan.restype = c_int
+    lib.mcl_apply_scan.argtypes = [c_void_p, c_void_p, c_int32, c_double]
+    lib.mcl_normalize.restype = c_int
+    lib.mcl_normalize.argtypes = [c_void_p, POINTER(c_double)]
+    lib.mcl_read_belief.restype = c_int
+    lib.mcl_read_belief.argtypes = [c_void_p, c_void_p, POINTER(Pose), POINTER(c_double), POINTER(c_double)]
+    lib.mcl_export_belief.restype = c_int
+    lib.mcl_export_belief.argtypes = [c_void_p, c_void_p, c_void_p]
+    lib.mcl_scan_sqdist.restype = c_int
+    lib.mcl_scan_sqdist.argtypes = [c_void_p, c_void_p, c_int32, c_void_p]
+    lib.mcl_get_info.restype = c_int
+    lib.mcl_get_info.argtypes = [c_void_p, c_int, POINTER(Info)]
+    lib.mcl_step_batch.restype = c_int
+    lib.mcl_step_batch.argtypes = [POINTER(c_void_p), c_void_p, c_int32, c_void_p]
+    _lib = lib
+    return lib
+
+
+def last_error() -> str:
+    return load_library().mcl_last_error().decode(errors="replace")
+
+
+def _check(status):
+    if status != OK:
+        raise MclError(status, last_error())
+
+
+def _stream_handle(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return c_void_p(s.cuda_stream)
+
+
+def _params(n_theta=1, sigma_xy=0.0, sigma_theta=0.0, radius_xy=-1, radius_theta=-1, storage="f32",
+            flags=DEFAULT_FLAGS) -> Params:
+    return Params(int(n_theta), float(sigma_xy), float(sigma_theta), int(radius_xy), int(radius_theta),
+                  DTYPES[storage] if isinstance(storage, str) else int(storage), int(flags))
+
+
+class Map:
+    """Traversability, wall weights and (optional) quantised range table on the GPU."""
+
+    def __init__(self, occupancy, cell_m, sigma_xy, *, radius_xy=-1, flags=DEFAULT_FLAGS,
+                 range_table=None, max_range_m=0.0, stream=None):
+        import torch
+        lib = load_library()
+        occ = np.ascontiguousarray(occupancy, dtype=np.uint8)
+        self.height, self.width = occ.shape
+        self.cell_m = float(cell_m)
+        self.sigma_xy = float(sigma_xy)
+        self.radius_xy = int(radius_xy)
+        self.flags = int(flags)
+        rt = None
+        n_dirs = 0
+        if range_table is not None:
+            rt = np.ascontiguousarray(range_table, dtype=np.float32)
+            n_dirs = rt.shape[-1]
+        self.n_dirs = n_dirs
+        self.max_range_m = float(max_range_m)
+        desc = MapDesc(self.width, self.height, self.cell_m, occ.ctypes.data,
+                       rt.ctypes.data if rt is not None else None, n_dirs, self.max_range_m)
+        prm = _params(sigma_xy=sigma_xy, radius_xy=radius_xy, flags=flags)
+        nbytes = lib.mcl_map_workspace_bytes(byref(desc), byref(prm))
+        if nbytes == 0:
+            _check(lib.mcl_map_create(byref(desc), byref(prm), None, 0, None, byref(c_void_p())))
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        h = c_void_p()
+        _check(lib.mcl_map_create(byref(desc), byref(prm), c_void_p(self.workspace.data_ptr()), nbytes,
+                                  _stream_handle(stream), byref(h)))
+        self.handle = h
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.mcl_map_destroy(self.handle)
+            self.handle = None
+
+
+class Filter:
+    """One belief tensor on the GPU (init_belief)."""
+
+    def __init__(self, map: Map, n_theta, sigma_theta, *, radius_theta=-1, storage="f32", init=None,
+                 theta0=0.0, stream=None):
+        import torch
+        lib = load_library()
+        self.map = map
+        self.n_theta = int(n_theta)
+        self.storage = storage
+        self.params = _params(n_theta, map.sigma_xy, sigma_theta, map.radius_xy, radius_theta, storage,
+                              map.flags)
+        nbytes = lib.mcl_filter_workspace_bytes(map.handle, byref(self.params))
+        if nbytes == 0:
+            _check(lib.mcl_init_belief(map.handle, byref(self.params), None, 0, None, None, 0.0,
+                                       byref(c_void_p())))
+        self.workspace_bytes = nbytes
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        init_ptr = None
+        if init is not None:
+            self._init = np.ascontiguousarray(init, dtype=np.float32)
+            assert self._init.shape == (self.n_theta, map.height, map.width)
+            init_ptr = self._init.ctypes.data
+        self.stream = stream
+        h = c_void_p()
+        _check(lib.mcl_init_belief(map.handle, byref(self.params), c_void_p(self.workspace.data_ptr()), nbytes,
+                                   _stream_handle(stream), init_ptr, float(theta0), byref(h)))
+        self.handle = h
+        self._init = None
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.mcl_filter_destroy(self.handle)
+            self.handle = None
+
+    # the five calls of the boundary, as methods
+    def step_odometry(self, u, v, w):
+        _check(_lib.mcl_step_odometry(self.handle, float(u), float(v), float(w)))
+
+    def apply_scan(self, ranges_m, sigma_m):
+        z = np.ascontiguousarray(ranges_m, dtype=np.float32)
+        _check(_lib.mcl_apply_scan(self.handle, z.ctypes.data, len(z), float(sigma_m)))
+
+    def normalize(self) -> float:
+        ln = c_double()
+        _check(_lib.mcl_normalize(self.handle, byref(ln)))
+        return ln.value
+
+    def read_belief(self, want_belief=True):
+        """Returns (belief float32 (T, H, W) or None, Pose, theta_offset, log_norm)."""
+        out = np.empty((self.n_theta, self.map.height, self.map.width), np.float32) if want_belief else None
+        pose = Pose()
+        th = c_double()
+        ln = c_double()
+        _check(_lib.mcl_read_belief(self.handle, out.ctypes.data if out is not None else None, byref(pose),
+                                    byref(th), byref(ln)))
+        return out, pose, th.value, ln.value
+
+    def export_belief(self, with_map=False):
+        """Normalised FP32 belief (and belief map) as CUDA tensors."""
+        import torch
+        out = torch.empty((self.n_theta, self.map.height, self.map.width), dtype=torch.float32, device="cuda")
+        bm = torch.empty((self.map.height, self.map.width), dtype=torch.float32, device="cuda") if with_map else None
+        _check(_lib.mcl_export_belief(self.handle, c_void_p(out.data_ptr()),
+                                      c_void_p(bm.data_ptr()) if bm is not None else None))
+        return (out, bm) if with_map else out
+
+    def scan_sqdist(self, ranges_m):
+        import torch
+        z = np.ascontiguousarray(ranges_m, dtype=np.float32)
+        out = torch.empty((self.n_theta, self.map.height, self.map.width), dtype=torch.int32, device="cuda")
+        _check(_lib.mcl_scan_sqdist(self.handle, z.ctypes.data, len(z), c_void_p(out.data_ptr())))
+        return out
+
+    def info(self, sync=True) -> Info:
+        inf = Info()
+        _check(_lib.mcl_get_info(self.handle, int(sync), byref(inf)))
+        return inf
+
+
+# ---- module-level names of the boundary --------------------------------------------
+
+def init_belief(map: Map, n_theta, sigma_theta, **kw) -> Filter:
+    return Filter(map, n_theta, sigma_theta, **kw)
+
+
+def step_odometry(f: Filter, u, v, w):
+    f.step_odometry(u, v, w)
+
+
+def apply_scan(f: Filter, ranges_m, sigma_m):
+    f.apply_scan(ranges_m, sigma_m)
+
+
+def normalize(f: Filter) -> float:
+    return f.normalize()
+
+
+def read_belief(f: Filter, want_belief=True):
+    return f.read_belief(want_belief)
+
+
+def step_batch(filters, uvw, stream=None):
+    """One odometry step for each filter (serving); uvw: (n, 3) float64."""
+    arr = (c_void_p * len(filters))(*[f.handle.value for f in filters])
+    u = np.ascontiguousarray(uvw, dtype=np.float64)
+    _check(load_library().mcl_step_batch(arr, u.ctypes.data, len(filters),
+                                         _stream_handle(stream)))

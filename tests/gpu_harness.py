@@ -1,0 +1,55 @@
+"""Shared helpers of the GPU parity tests: run the HIP path and the oracle side by side."""
+
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+
+try:
+    import torch
+    HAVE_GPU = torch.cuda.is_available()
+except Exception:  # pragma: no cover
+    HAVE_GPU = False
+
+needs_gpu = pytest.mark.skipif(not HAVE_GPU, reason="needs a GPU")
+
+# FP32 bound on the peak-normalised max-abs error against the FP64 oracle.
+FP32_PEAK_TOL = 1e-5
+# argmax agreement: the GPU argmax lies in the oracle's tie set {B >= max (1 - tau)}
+FP32_TIE_TAU = 1e-6
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def oracle_params(n_theta, cell, sxy, sth, rxy=-1, rth=-1, flags=3):
+    return O.OracleParams(n_theta=n_theta, cell_m=cell, sigma_xy=sxy, sigma_theta=sth, radius_xy=rxy,
+                          radius_theta=rth, mask_before_blur=bool(flags & 1),
+                          wall_normalize=bool(flags & 2), subcell_gate=bool(flags & 4))
+
+
+def make_gpu(occ, cell, n_theta, sxy, sth, rxy=-1, rth=-1, storage="f32", flags=3, init=None, theta0=0.0,
+             range_table=None, max_range_m=0.0):
+    from paper_1910_00572_amd import mcl
+    m = mcl.Map(occ, cell, sxy, radius_xy=rxy, flags=flags, range_table=range_table, max_range_m=max_range_m)
+    f = mcl.Filter(m, n_theta, sth, radius_theta=rth, storage=storage, init=init, theta0=theta0)
+    return m, f
+
+
+def peak_err(gpu_b, ref_b):
+    return float(np.abs(gpu_b.astype(np.float64) - ref_b).max() / ref_b.max())
+
+
+def l1_err(gpu_b, ref_b):
+    return float(np.abs(gpu_b.astype(np.float64) - ref_b).sum())
+
+
+def in_tie_set(pose_kji, ref_b, tau):
+    k, j, i = pose_kji
+    return bool(ref_b[k, j, i] >= ref_b.max() * (1.0 - tau))

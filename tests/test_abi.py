@@ -1,0 +1,61 @@
+"""The C-ABI library loads and exports every symbol include/mcl.h declares (CPU only).
+
+No compute call is made here: without a GPU only symbol resolution and the
+host-side argument checks that run before any device work are exercised.
+"""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1910_00572_amd import mcl
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _header_symbols():
+    text = open(os.path.join(ROOT, "include", "mcl.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(mcl_[a-z_]+)\s*\(", text)))
+
+
+def test_header_and_binding_agree():
+    assert _header_symbols() == sorted(mcl.ABI_SYMBOLS)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = mcl.load_library()
+    for name in _header_symbols():
+        assert hasattr(lib, name), name
+
+
+def test_struct_layouts_match_header():
+    # offsets the C compiler gives these structs on x86-64 (natural alignment)
+    assert ctypes.sizeof(mcl.MapDesc) == 48
+    assert ctypes.sizeof(mcl.Params) == 40
+    assert ctypes.sizeof(mcl.Pose) == 48
+    assert mcl.Info.steps.offset == 40 and ctypes.sizeof(mcl.Info) == 88
+
+
+def test_argument_errors_before_any_device_work():
+    lib = mcl.load_library()
+    desc = mcl.MapDesc(0, 10, 0.1, None, None, 0, 0.0)
+    prm = mcl._params(4, 1.0, 1.0)
+    assert lib.mcl_map_workspace_bytes(ctypes.byref(desc), ctypes.byref(prm)) == 0
+    h = ctypes.c_void_p()
+    st = lib.mcl_map_create(ctypes.byref(desc), ctypes.byref(prm), None, 0, None, ctypes.byref(h))
+    assert st == mcl.EINVAL and "map size" in mcl.last_error()
+    occ = (ctypes.c_uint8 * 100)()
+    desc = mcl.MapDesc(10, 10, 0.1, ctypes.addressof(occ), None, 0, 0.0)
+    big = mcl._params(4, 2.0, 1.0)  # radius ceil(6) > 4
+    assert lib.mcl_map_workspace_bytes(ctypes.byref(desc), ctypes.byref(big)) == 0
+    ok = mcl._params(4, 1.0, 1.0)
+    n = lib.mcl_map_workspace_bytes(ctypes.byref(desc), ctypes.byref(ok))
+    assert n > 0
+    st = lib.mcl_map_create(ctypes.byref(desc), ctypes.byref(ok), ctypes.c_void_p(1 << 20), n - 1, None,
+                            ctypes.byref(h))
+    assert st == mcl.ENOMEM
+    assert lib.mcl_step_odometry(None, 0.0, 0.0, 0.0) == mcl.EINVAL
+    assert lib.mcl_normalize(None, None) == mcl.EINVAL
