@@ -83,6 +83,130 @@ def cpu_baseline(occ, odo, n_theta, sigma, steps=8):
                       f"{dt:.1f} s"}
 
 
+def bench_mixed_precision(steps):
+    """1024x1024 map, 128 bins: FP32 vs BF16 storage on the same trajectory."""
+    import torch
+    from gen import rooms_and_corridors, smooth_trajectory
+    from paper_1910_00572_amd import mcl
+    occ = rooms_and_corridors(1024, 1024, seed=5)
+    _, odo = smooth_trajectory(occ, 0.05, steps + 10, seed=6)
+    m = mcl.Map(occ, 0.05, 1.0)
+    states = occ.size * 128
+    out = {}
+    beliefs = {}
+    for storage, eb in (("f32", 4), ("bf16", 2)):
+        f = mcl.Filter(m, 128, 1.0, storage=storage)
+        elapsed, lat = time_filter(f, odo, steps, 5, 20)
+        b, pose, _, _ = f.read_belief()
+        beliefs[storage] = (b, pose.as_tuple())
+        kern = float(lat.mean())
+        out[storage] = {"states_steps_per_s": states * steps / elapsed, "ms_per_step": elapsed * 1e3 / steps,
+                        "event_mean_ms": kern,
+                        "roofline_frac": 2 * states * eb / (kern * 1e-3) / 1e9 / HBM_PEAK_GBS}
+        del f
+        torch.cuda.empty_cache()
+    bf, f32 = beliefs["bf16"][0].astype(np.float64), beliefs["f32"][0].astype(np.float64)
+    k, j, i = beliefs["bf16"][1]
+    out["bf16_vs_f32_after_steps"] = {"steps": steps + 5 + 20, "l1": float(np.abs(bf - f32).sum()),
+                                     "peak_normalised_max_abs": float(np.abs(bf - f32).max() / f32.max()),
+                                     "argmax_in_f32_tie_set_2^-7": bool(f32[k, j, i] >= f32.max() * (1 - 2 ** -7))}
+    out["speedup_bf16_over_f32"] = out["bf16"]["states_steps_per_s"] / out["f32"]["states_steps_per_s"]
+    return out
+
+
+def bench_scan(n_scans):
+    """512x512 map, 72 bins, 360 beams: dense scan update, BF16 and FP32 matrix operands."""
+    import torch
+    from gen import noisy_scan, range_table, rooms_and_corridors, smooth_trajectory
+    from paper_1910_00572_amd import mcl
+    occ = rooms_and_corridors(512, 512, seed=3)
+    poses, odo = smooth_trajectory(occ, 0.05, 100, seed=4)
+    R = range_table(occ, 0.05, 360, 10.0)
+    out = {}
+    for name, flags in (("bf16_mfma", mcl.DEFAULT_FLAGS), ("f32_mfma", mcl.DEFAULT_FLAGS | mcl.SCAN_F32)):
+        m = mcl.Map(occ, 0.05, 1.0, range_table=R, max_range_m=10.0, flags=flags)
+        f = mcl.Filter(m, 72, 1.0, storage="f32")
+        zs = [noisy_scan(occ, 0.05, poses[(10 * t) % 100], 360, 10.0, 0.1, seed=7 + t) for t in range(n_scans)]
+        for t in range(10):
+            f.step_odometry(*odo[t])
+        f.apply_scan(zs[0], 0.1)
+        torch.cuda.synchronize()
+        stream = torch.cuda.current_stream()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in zs]
+        for t, z in enumerate(zs):
+            ev[t][0].record(stream)
+            f.apply_scan(z, 0.1)
+            ev[t][1].record(stream)
+        torch.cuda.synchronize()
+        ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+        useful = 2.0 * 512 * 512 * 360 * 72
+        issued = 2.0 * 512 * 512 * 384 * 96
+        peak = 2500e12 if name == "bf16_mfma" else 157.3e12
+        # scan every 10 steps over 100 steps
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for t in range(100):
+            f.step_odometry(*odo[t])
+            if t % 10 == 9:
+                f.apply_scan(zs[(t // 10) % len(zs)], 0.1)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        out[name] = {"scan_ms": ms, "useful_gflop": useful / 1e9, "issued_gflop": issued / 1e9,
+                     "achieved_tflops_useful": useful / (ms * 1e-3) / 1e12,
+                     "mfma_frac_of_peak_issued": issued / (ms * 1e-3) / peak,
+                     "table_bytes": 512 * 512 * 384 * (2 if name == "bf16_mfma" else 4),
+                     "hbm_frac_table_plus_belief_rw": (512 * 512 * 384 * (2 if name == "bf16_mfma" else 4)
+                                                       + 4 * 512 * 512 * 72 * 4) / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                     "steps_with_scan_every_10_states_steps_per_s": 512 * 512 * 72 * 100 / dt}
+        del f, m
+        torch.cuda.empty_cache()
+    return out
+
+
+def bench_serving(n_requests, seed=8, capacity=None):
+    """Poisson stream of mixed filters (grid 128..1024, 36/72 bins, FP32/BF16, scans on half)."""
+    import torch
+    from gen import noisy_scan, random_odometry, range_table, rooms_and_corridors
+    from paper_1910_00572_amd import mcl
+    from paper_1910_00572_amd.serve import Request, Server
+    rng = np.random.default_rng(seed)
+    grids = (128, 256, 512, 1024)
+    maps, occs = {}, {}
+    for g in grids:
+        occ = rooms_and_corridors(g, g, seed=100 + g)
+        occs[g] = occ
+        maps[g] = mcl.Map(occ, 0.05, 1.0, range_table=range_table(occ, 0.05, 360, 10.0), max_range_m=10.0)
+    reqs = []
+    total = 0.0
+    for rid in range(n_requests):
+        g = int(rng.choice(grids))
+        n_theta = int(rng.choice([36, 72]))
+        storage = str(rng.choice(["f32", "bf16"]))
+        steps = int(rng.integers(50, 501))
+        odo = random_odometry(steps, seed=1000 + rid, max_step_m=0.1)
+        scans = {}
+        if rid % 2 == 0:
+            free = np.argwhere(occs[g] == 0)
+            for t in range(9, steps, 10):
+                j, i = free[rng.integers(len(free))]
+                scans[t] = noisy_scan(occs[g], 0.05, ((i + 0.5) * 0.05, (j + 0.5) * 0.05, rng.uniform(-3, 3)),
+                                      360, 10.0, 0.1, seed=rid * 1000 + t)
+        total += g * g * n_theta * steps
+        reqs.append(Request(rid, 0.0, g, n_theta, storage, odo, scans))
+    cap = capacity or 5e11
+    span = total / (0.7 * cap)
+    arr = np.cumsum(rng.exponential(span / n_requests, n_requests))
+    for r, a in zip(reqs, arr):
+        r.arrival_s = float(a)
+    server = Server(maps, 16 << 30, max_active=256)
+    results, stats = server.run(reqs)
+    stats["offered_states_steps_per_s"] = total / span
+    stats["hbm_budget_gib"] = 16
+    del server, maps
+    torch.cuda.empty_cache()
+    return stats
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -91,7 +215,8 @@ def main():
     ap.add_argument("--latency-steps", type=int, default=200)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=8)
-    ap.add_argument("--only", default="")
+    ap.add_argument("--no-extra", action="store_true", help="headline workload only")
+    ap.add_argument("--serving-requests", type=int, default=256)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: the filter step is a single-GPU kernel and this build "
@@ -141,6 +266,16 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None},
     }
+    del f, m
+    torch.cuda.empty_cache()
+    if not args.no_extra:
+        log("[bench] 1024x1024x128 FP32 vs BF16")
+        out["mixed_precision_1024x1024x128"] = bench_mixed_precision(100)
+        log("[bench] scan update 512x512x72, 360 beams")
+        out["scan_512x512x72_360beams"] = bench_scan(20)
+        if args.serving_requests > 0:
+            log(f"[bench] serving {args.serving_requests} requests")
+            out["serving"] = bench_serving(args.serving_requests, capacity=value)
     if not args.no_cpu_baseline:
         log("[bench] timing the FP64 oracle on the host")
         out["cpu_baseline"] = cpu_baseline(occ, odo, n_theta, sigma, args.cpu_steps)

@@ -186,12 +186,22 @@ mcl_status mcl_scan_sqdist(mcl_filter f, const float* ranges_m, int32_t n_beams,
  * log_norm and status are current. */
 mcl_status mcl_get_info(mcl_filter f, int sync, mcl_info* out);
 
-/* step_batch (async, serving): one odometry step for each of n filters, in
- * as few launches as their storage types and radii allow, on `stream`
- * (NULL = each filter's own stream must then be the same).  uvw holds 3
- * doubles per filter.  Each filter's result is bitwise identical to calling
- * mcl_step_odometry on it alone.  Filters must be distinct. */
-mcl_status mcl_step_batch(mcl_filter* const filters, const double* uvw, int32_t n, void* stream);
+/* Device bytes the batch job table of mcl_step_batch needs for up to
+ * max_filters filters (0 if out of range). */
+size_t mcl_batch_workspace_bytes(int32_t max_filters);
+
+/* step_batch (async, serving): one odometry step (as mcl_step_odometry) for
+ * each of n distinct filters, enqueued on `stream` as one launch per group of
+ * filters that share a storage type, blur radius and launch shape; filters of
+ * any grid size and heading count mix in one launch.  uvw holds 3 doubles
+ * (u, v, w) per filter.  dev_ws is caller-owned device memory of at least
+ * mcl_batch_workspace_bytes(n) bytes holding the job table; it must not be
+ * reused until the launches complete (stream order).  Each filter's result is
+ * bitwise identical to stepping it alone: its tiles, reduction order and
+ * final reduction do not depend on the batch.  All filters must have been
+ * created on `stream` or be ordered with it by the caller. */
+mcl_status mcl_step_batch(mcl_filter* const filters, const double* uvw, int32_t n, void* dev_ws,
+                          size_t ws_bytes, void* stream);
 
 #ifdef __cplusplus
 }

@@ -6,5 +6,5 @@ The hot path lives in libmcl.so (HIP for gfx950, C ABI in include/mcl.h);
 
 from .mcl import (  # noqa: F401
     Map, Filter, MclError, init_belief, step_odometry, apply_scan, normalize, read_belief, step_batch,
-    load_library, ABI_SYMBOLS,
+    load_library, ABI_SYMBOLS, BatchWorkspace,
 )

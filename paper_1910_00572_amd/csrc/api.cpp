@@ -114,7 +114,7 @@ struct mcl_map_s {
 };
 
 struct StepShape {
-  int tx = 64, ty = 16, nt = 256, chunks = 1, chunk_len = 1, tiles_x = 1, tiles_y = 1;
+  int tx = 0, ty = 16, nt = 256, chunks = 1, chunk_len = 1, tiles_x = 1, tiles_y = 1;
   int blocks() const { return tiles_x * tiles_y * chunks; }
 };
 
@@ -146,9 +146,13 @@ namespace {
 
 constexpr int kReduceBlocks = 1024;
 
+// Launch shape of the step kernel.  Default: the streaming kernel (tx = 0):
+// strips of 63 - 2R columns by 16 rows, 4 waves per workgroup.  The tiled
+// kernel (tx = 64 or 32) stays selectable.  MCL_STEP_SHAPE="tx,ty,nt[,chunks]"
+// overrides the shape (tuning).
 StepShape choose_shape(int W, int H, int T, int R) {
   StepShape s;
-  int sh[4] = {64, 16, 256, 0};
+  int sh[4] = {0, 16, 256, 0};
   if (const char* env = getenv("MCL_STEP_SHAPE")) {
     int a = 0, b = 0, c = 0, d = 0;
     if (sscanf(env, "%d,%d,%d,%d", &a, &b, &c, &d) >= 3) {
@@ -161,7 +165,8 @@ StepShape choose_shape(int W, int H, int T, int R) {
   s.tx = sh[0];
   s.ty = sh[1];
   s.nt = sh[2];
-  s.tiles_x = (W + s.tx - 1) / s.tx;
+  const int strip = s.tx > 0 ? s.tx : 63 - 2 * R;
+  s.tiles_x = (W + strip - 1) / strip;
   s.tiles_y = (H + s.ty - 1) / s.ty;
   const int tiles = s.tiles_x * s.tiles_y;
   int chunks = sh[3];
@@ -552,22 +557,153 @@ mcl_status mcl_get_info(mcl_filter f, int sync, mcl_info* out) {
   return MCL_OK;
 }
 
-mcl_status mcl_apply_scan(mcl_filter f, const float* ranges_m, int32_t n_beams, double sigma_m) {
+static mcl_status scan_common(mcl_filter f, const float* ranges_m, int32_t n_beams, double sigma_m,
+                              int32_t* dout) {
   if (!f) return fail(MCL_EINVAL, "filter is NULL");
-  return scan_apply(f, ranges_m, n_beams, sigma_m);
+  const ScanTable& t = f->map->scan;
+  if (t.n_dirs == 0) return fail(MCL_ESTATE, "the map has no range table");
+  if (!ranges_m) return fail(MCL_EINVAL, "ranges is NULL");
+  if (n_beams != t.n_dirs) return fail(MCL_EINVAL, "n_beams %d differs from the table's %d directions", n_beams, t.n_dirs);
+  if (!dout && (!(sigma_m > 0.0) || !isfinite(sigma_m))) return fail(MCL_EINVAL, "sigma_m must be > 0");
+  for (int b = 0; b < n_beams; ++b)
+    if (!isfinite(ranges_m[b])) return fail(MCL_EINVAL, "range %d is not finite", b);
+  ScanLaunch L;
+  L.table = &t;
+  L.work = f->scanw;
+  L.buf[0] = f->buf[0];
+  L.buf[1] = f->buf[1];
+  L.scratch = f->scan_scratch;
+  L.partials = f->partials;
+  L.dev = f->dev;
+  L.W = f->map->W;
+  L.H = f->map->H;
+  L.pitch = f->map->pitch;
+  L.n_theta = f->T;
+  L.dtype = f->dtype;
+  L.sstride = f->sstride;
+  L.theta = f->theta;
+  L.stream = f->stream;
+  HIP_TRY(scan_launch(L, ranges_m, sigma_m, dout), "scan launch");
+  return MCL_OK;
+}
+
+mcl_status mcl_apply_scan(mcl_filter f, const float* ranges_m, int32_t n_beams, double sigma_m) {
+  return scan_common(f, ranges_m, n_beams, sigma_m, nullptr);
 }
 
 mcl_status mcl_scan_sqdist(mcl_filter f, const float* ranges_m, int32_t n_beams, int32_t* dev_out) {
-  if (!f) return fail(MCL_EINVAL, "filter is NULL");
-  return scan_sqdist(f, ranges_m, n_beams, dev_out);
+  if (!dev_out) return fail(MCL_EINVAL, "dev_out is NULL");
+  return scan_common(f, ranges_m, n_beams, 1.0, dev_out);
 }
 
-mcl_status mcl_step_batch(mcl_filter* const filters, const double* uvw, int32_t n, void* stream) {
-  (void)filters;
-  (void)uvw;
-  (void)n;
-  (void)stream;
-  return fail(MCL_ESTATE, "step_batch is not available in this build");
+static size_t batch_bytes(int32_t n) {
+  Carver c(nullptr);
+  c.take(static_cast<size_t>(n) * sizeof(StepArgs));
+  c.take(static_cast<size_t>(2 * n + 2) * sizeof(int32_t));
+  return c.off;
+}
+
+size_t mcl_batch_workspace_bytes(int32_t max_filters) {
+  if (max_filters < 1 || max_filters > 65536) return 0;
+  return batch_bytes(max_filters);
+}
+
+mcl_status mcl_step_batch(mcl_filter* const filters, const double* uvw, int32_t n, void* dev_ws, size_t ws_bytes,
+                          void* stream) {
+  if (!filters || !uvw || n < 1 || n > 65536) return fail(MCL_EINVAL, "filters/uvw NULL or n out of range");
+  if (!dev_ws) return fail(MCL_EINVAL, "workspace is NULL");
+  if (ws_bytes < batch_bytes(n)) return fail(MCL_ENOMEM, "batch workspace needs %zu bytes", batch_bytes(n));
+  for (int i = 0; i < n; ++i) {
+    if (!filters[i]) return fail(MCL_EINVAL, "filter %d is NULL", i);
+    for (int j = 0; j < i; ++j)
+      if (filters[j] == filters[i]) return fail(MCL_EINVAL, "filter %d appears twice", i);
+    const double* o = uvw + 3 * i;
+    if (!isfinite(o[0]) || !isfinite(o[1]) || !isfinite(o[2])) return fail(MCL_EINVAL, "odometry %d not finite", i);
+    const double cell = filters[i]->map->cell;
+    if (fabs(o[0]) / cell > 1e6 || fabs(o[1]) / cell > 1e6) return fail(MCL_EINVAL, "odometry %d too large", i);
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  // Host bookkeeping identical to mcl_step_odometry; a filter whose sub-cell
+  // gate does not fire takes no launch.
+  struct Job {
+    StepArgs a;
+    int dtype, radius, tx, ty, nt;
+  };
+  std::vector<Job> jobs;
+  jobs.reserve(n);
+  for (int i = 0; i < n; ++i) {
+    mcl_filter f = filters[i];
+    const double u = uvw[3 * i], v = uvw[3 * i + 1], w = uvw[3 * i + 2];
+    const double cell = f->map->cell;
+    StepArgs a = make_step_args(f);
+    if (f->map->flags & MCL_SUBCELL_GATE) {
+      const double c = cos(f->theta), sn = sin(f->theta);
+      const double ax = f->acc_x + u * c - v * sn;
+      const double ay = f->acc_y + u * sn + v * c;
+      f->theta += w;
+      ++f->steps;
+      if (hypot(ax, ay) < cell) {
+        f->acc_x = ax;
+        f->acc_y = ay;
+        continue;
+      }
+      f->acc_x = f->acc_y = 0.0;
+      a.u_cells = ax / cell;
+      a.v_cells = ay / cell;
+      a.theta_prev = 0.0;
+    } else {
+      a.u_cells = u / cell;
+      a.v_cells = v / cell;
+      a.theta_prev = f->theta;
+      f->theta += w;
+      ++f->steps;
+    }
+    jobs.push_back(Job{a, f->dtype, f->radius, f->shape.tx, f->shape.ty, f->shape.nt});
+  }
+  if (jobs.empty()) return MCL_OK;
+  auto same = [](const Job& x, const Job& y) {
+    return x.dtype == y.dtype && x.radius == y.radius && x.tx == y.tx && x.ty == y.ty && x.nt == y.nt;
+  };
+  auto less = [](const Job& x, const Job& y) {
+    if (x.dtype != y.dtype) return x.dtype < y.dtype;
+    if (x.radius != y.radius) return x.radius < y.radius;
+    if (x.tx != y.tx) return x.tx < y.tx;
+    if (x.ty != y.ty) return x.ty < y.ty;
+    return x.nt < y.nt;
+  };
+  std::stable_sort(jobs.begin(), jobs.end(), less);
+  // per group: its jobs, then njobs+1 first-block offsets relative to the group
+  std::vector<StepArgs> args;
+  std::vector<int32_t> first;
+  struct Group {
+    int dtype, radius, tx, ty, nt, job0, first0, njobs, blocks;
+  };
+  std::vector<Group> groups;
+  for (size_t i = 0; i < jobs.size(); ++i) {
+    if (i == 0 || !same(jobs[i], jobs[i - 1])) {
+      if (!groups.empty()) first.push_back(groups.back().blocks);
+      groups.push_back(Group{jobs[i].dtype, jobs[i].radius, jobs[i].tx, jobs[i].ty, jobs[i].nt,
+                             static_cast<int>(args.size()), static_cast<int>(first.size()), 0, 0});
+    }
+    Group& g = groups.back();
+    first.push_back(g.blocks);
+    args.push_back(jobs[i].a);
+    g.blocks += jobs[i].a.tiles_x * jobs[i].a.tiles_y * jobs[i].a.chunks;
+    ++g.njobs;
+  }
+  first.push_back(groups.back().blocks);
+  Carver c(dev_ws);
+  StepArgs* args_dev = static_cast<StepArgs*>(c.take(args.size() * sizeof(StepArgs)));
+  int32_t* first_dev = static_cast<int32_t*>(c.take(first.size() * sizeof(int32_t)));
+  HIP_TRY(hipMemcpyAsync(args_dev, args.data(), args.size() * sizeof(StepArgs), hipMemcpyHostToDevice, s),
+          "batch jobs upload");
+  HIP_TRY(hipMemcpyAsync(first_dev, first.data(), first.size() * sizeof(int32_t), hipMemcpyHostToDevice, s),
+          "batch offsets upload");
+  for (const Group& g : groups)
+    HIP_TRY(launch_step_batch(g.dtype, g.radius, g.tx, g.ty, g.nt, args_dev + g.job0, first_dev + g.first0, g.njobs,
+                              g.blocks, s),
+            "batch launch");
+  return MCL_OK;
 }
 
 }  // extern "C"

@@ -86,8 +86,9 @@ struct Carver {
 // Return hipSuccess or the launch error.
 hipError_t launch_step(int dtype, int radius, int tx, int ty, int nt, const StepArgs& a,
                        hipStream_t s);
+// jobs_dev[0..njobs) with first_dev[j] = first workgroup of job j (first_dev[njobs] = total).
 hipError_t launch_step_batch(int dtype, int radius, int tx, int ty, int nt, const StepArgs* jobs_dev,
-                             const int32_t* block_job_dev, int32_t total_blocks, hipStream_t s);
+                             const int32_t* first_dev, int32_t njobs, int32_t total_blocks, hipStream_t s);
 bool step_config_supported(int dtype, int radius, int tx, int ty, int nt);
 
 hipError_t launch_map_setup(const uint8_t* occ_dev, int W, int H, int pitch, const double* gxy,

@@ -23,13 +23,30 @@ struct ScanTable {
 // Per-filter scan scratch (circulant operand, per-tile partials).
 struct ScanWork {
   void* c = nullptr;       // [n_theta_pad][kpad] circulant scan operand
-  int32_t* zs = nullptr;   // device copy of the quantised scan and offsets
 };
 
+// Partials the scan needs: one per 128-cell tile of pass 1, two per pass-2 block.
 inline int kScanMaxBlocks(int W, int H, int pitch) {
   (void)W;
-  return static_cast<int>((static_cast<int64_t>(H) * pitch + 255) / 256);
+  return static_cast<int>((static_cast<int64_t>(H) * pitch + 127) / 128) + 2048;
 }
+
+// Everything one scan update needs from the filter handle.
+struct ScanLaunch {
+  const ScanTable* table;
+  ScanWork work;
+  void* buf[2];
+  float* scratch;     // FP32, n_theta * H * pitch
+  double* partials;
+  FilterDev* dev;
+  int W, H, pitch, n_theta, dtype;
+  int64_t sstride;
+  double theta;       // heading offset at the time of the scan
+  hipStream_t stream;
+};
+
+// Enqueue the scan update (dout == nullptr) or the diagnostic distance output.
+hipError_t scan_launch(const ScanLaunch& L, const float* ranges_m, double sigma_m, int32_t* dout);
 size_t scan_work_bytes(int n_theta, int kpad);
 ScanWork scan_work_carve(void* base, int n_theta, int kpad);
 ScanTable scan_table_carve(Carver& c, const mcl_map_desc* d, int pitch, bool f32);
@@ -37,5 +54,3 @@ mcl_status scan_table_build(ScanTable& t, const mcl_map_desc* d, int pitch, hipS
 
 }  // namespace mcl
 
-mcl_status scan_apply(mcl_filter f, const float* ranges_m, int32_t n_beams, double sigma_m);
-mcl_status scan_sqdist(mcl_filter f, const float* ranges_m, int32_t n_beams, int32_t* dev_out);

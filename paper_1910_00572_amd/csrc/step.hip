@@ -99,6 +99,59 @@ __device__ inline int xcd_remap(int b, int n) {
   return (x < r) ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
 }
 
+// Job of global workgroup g: the largest j with first[j] <= g.
+__device__ inline int find_job(const int32_t* __restrict__ first, int njobs, int g) {
+  int lo = 0, hi = njobs - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (first[mid] <= g) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Run by every thread of the last workgroup to arrive: reduce all partials in
+// a fixed order and update the filter scalars (renormalisation bookkeeping).
+template <int NT>
+__device__ void finalize_step(const StepArgs& a, FilterDev* dev, int nblk, float scale, int cur, double* red_s,
+                              float* red_m) {
+  const int t = threadIdx.x;
+  double s = 0.0;
+  float mx = 0.f;
+  for (int b = t; b < nblk; b += NT) {
+    s += __hip_atomic_load(&a.partials[2 * b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    mx = fmaxf(mx, static_cast<float>(__hip_atomic_load(&a.partials[2 * b + 1], __ATOMIC_RELAXED,
+                                                        __HIP_MEMORY_SCOPE_AGENT)));
+  }
+  red_s[t] = s;
+  red_m[t] = mx;
+  __syncthreads();
+#pragma unroll
+  for (int st = NT / 2; st > 0; st >>= 1) {
+    if (t < st) {
+      red_s[t] += red_s[t + st];
+      red_m[t] = fmaxf(red_m[t], red_m[t + st]);
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    const double tot = red_s[0];
+    const float m = red_m[0];
+    if (!(tot > 0.0) || !isfinite(tot) || !(m > 0.f)) {
+      dev->status = kStatusDegenerate;  // keep the previous belief (cur unchanged)
+    } else {
+      dev->log_norm += log(tot) - log(static_cast<double>(scale)) - dev->lnsum;
+      dev->lnsum = log(tot);
+      dev->sum = tot;
+      dev->maxval = m;
+      const double sc = 1.0 / static_cast<double>(m);
+      dev->scale = sc > static_cast<double>(FLT_MAX) ? FLT_MAX : static_cast<float>(sc);
+      dev->cur = cur ^ 1;
+    }
+    __hip_atomic_store(&dev->counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
 template <typename T, int R, int TX, int TY, int NT>
 __device__ __forceinline__ void step_body(const StepArgs& a, const int blk, const int nblk) {
   constexpr int VEC = Store<T>::VEC;
@@ -389,40 +442,276 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int blk, cons
   __syncthreads();
   if (!last_flag) return;
 
-  double s = 0.0;
-  float mx = 0.f;
-  for (int b = t; b < nblk; b += NT) {
-    s += __hip_atomic_load(&a.partials[2 * b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    mx = fmaxf(mx, static_cast<float>(__hip_atomic_load(&a.partials[2 * b + 1], __ATOMIC_RELAXED,
-                                                        __HIP_MEMORY_SCOPE_AGENT)));
+  finalize_step<NT>(a, dev, nblk, scale, cur, red_s, red_m);
+}
+
+// ---- streaming variant ------------------------------------------------------------
+// One wave owns a strip of 64 consecutive columns (lane = column) and streams
+// the TY + 2R + 1 source rows of a channel through registers: the bilinear
+// x neighbour comes from the adjacent lane (DPP wave shift), the y
+// interpolation, mask and y blur run down a register window, and the x blur
+// uses DPP shifts of the y-blurred rows.  Lanes R+1 .. 63-R hold valid
+// outputs (63 - 2R columns per strip).  The waves of a workgroup take
+// consecutive channels; the theta blur reads a ring of 2R + WAVES channel
+// results in LDS (layout [slot][lane][row], 16-byte reads of four rows),
+// with two barriers per group of WAVES channels.  The next group's source
+// rows are loaded while the current group is computed.
+//
+// Rows are read and written through raw buffer descriptors built per row on
+// the scalar unit: the lane offset is the column, a row outside the grid gets
+// an empty descriptor, and the hardware returns 0 for (and drops stores to)
+// out-of-range offsets, so no per-row vector address arithmetic or branch is
+// needed.
+constexpr int kRsrcWord3 = 0x00020000;  // raw buffer, 32-bit data (gfx9 family)
+
+template <typename T>
+struct Elt;
+template <>
+struct Elt<float> {
+  static constexpr int BYTES = 4;
+  __device__ static inline float load(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+    return __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0);
   }
-  red_s[t] = s;
-  red_m[t] = mx;
+  __device__ static inline void store(float v, __amdgpu_buffer_rsrc_t r, uint32_t off) {
+    __builtin_amdgcn_raw_buffer_store_b32(v, r, off, 0, 0);
+  }
+};
+template <>
+struct Elt<__bf16> {
+  static constexpr int BYTES = 2;
+  __device__ static inline float load(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+    return __uint_as_float(static_cast<uint32_t>(__builtin_amdgcn_raw_buffer_load_b16(r, off, 0, 0)) << 16);
+  }
+  __device__ static inline void store(float v, __amdgpu_buffer_rsrc_t r, uint32_t off) {
+    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, static_cast<__bf16>(v)), r, off, 0, 0);
+  }
+};
+template <>
+struct Elt<_Float16> {
+  static constexpr int BYTES = 2;
+  __device__ static inline float load(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+    return static_cast<float>(__builtin_bit_cast(_Float16, __builtin_amdgcn_raw_buffer_load_b16(r, off, 0, 0)));
+  }
+  __device__ static inline void store(float v, __amdgpu_buffer_rsrc_t r, uint32_t off) {
+    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, static_cast<_Float16>(v)), r, off, 0, 0);
+  }
+};
+
+__device__ inline __amdgpu_buffer_rsrc_t row_rsrc(const void* row, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(row), static_cast<short>(0), static_cast<int>(bytes),
+                                           kRsrcWord3);
+}
+
+// lane i receives lane i-1 / i+1; lanes without a source receive 0
+__device__ inline float from_left(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x138, 0xf, 0xf, true));
+}
+__device__ inline float from_right(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x130, 0xf, 0xf, true));
+}
+
+template <typename T, int R, int TY, int WAVES>
+__device__ __forceinline__ void stream_body(const StepArgs& a, const int blk, const int nblk) {
+  constexpr int NT = 64 * WAVES;
+  constexpr int TXW = 63 - 2 * R;  // valid output columns per strip
+  constexpr int NS = TY + 2 * R;   // S rows
+  constexpr int NR = NS + 1;       // source rows
+  constexpr int RS = 2 * R + WAVES;
+  constexpr int TAPS = 2 * R + 1;
+  constexpr int LP = TY + 4;       // ring lane pitch (floats): conflict-free 16-byte accesses
+  constexpr int EB = Elt<T>::BYTES;
+  static_assert(TY % 4 == 0, "rows per strip must be a multiple of 4");
+
+  __shared__ __attribute__((aligned(16))) float ring[RS][64][LP];
+  __shared__ int pnx[kMaxTheta], pny[kMaxTheta];
+  __shared__ float pfx[kMaxTheta], pfy[kMaxTheta];
+  __shared__ double red_s[NT];
+  __shared__ float red_m[NT];
+  __shared__ int last_flag;
+
+  const int t = threadIdx.x;
+  const int lane = t & 63;
+  const int w = __builtin_amdgcn_readfirstlane(t >> 6);  // wave index, uniform per wave
+  const int H = a.H, pitch = a.pitch, nth = a.n_theta;
+  const int64_t sstride = a.sstride;
+  const uint32_t row_bytes = static_cast<uint32_t>(pitch) * EB;
+  const int tiles_x = a.tiles_x;
+  const int ntile = tiles_x * a.tiles_y;
+  const int chunk = blk / ntile, tile = blk % ntile;
+  const int xb = (tile % tiles_x) * TXW - (R + 1);
+  const int y0 = (tile / tiles_x) * TY;
+  const int x = xb + lane;
+  const int kbeg = chunk * a.chunk_len;
+  const int kend = min(nth, kbeg + a.chunk_len);
+  const int nk = kend - kbeg;
+  const int count = nk + 2 * R;
+  const int jbeg = kbeg - R;
+  FilterDev* dev = a.dev;
+  const int cur = dev->cur;
+  const float scale = dev->scale;
+  const T* __restrict__ bin = static_cast<const T*>(a.buf[cur]);
+  T* __restrict__ bout = static_cast<T*>(a.buf[cur ^ 1]);
+  const double u = a.u_cells, v = a.v_cells, th0 = a.theta_prev, dth = a.dtheta;
+
+  for (int k = t; k < nth; k += NT) {
+    double sn, cs;
+    sincos(th0 + k * dth, &sn, &cs);
+    const double dx = u * cs - v * sn;
+    const double dy = u * sn + v * cs;
+    const double fdx = floor(dx), fdy = floor(dy);
+    pnx[k] = static_cast<int>(fdx);
+    pny[k] = static_cast<int>(fdy);
+    pfx[k] = static_cast<float>(dx - fdx);
+    pfy[k] = static_cast<float>(dy - fdy);
+  }
+  float gx[TAPS], gt[TAPS];
+#pragma unroll
+  for (int l = 0; l < TAPS; ++l) {
+    gx[l] = a.gxy[l];
+    gt[l] = a.gth[l];
+  }
+  const bool xin = x >= 0 && x < pitch;
+  float mreg[NS];
+#pragma unroll
+  for (int r = 0; r < NS; ++r) {
+    const int y = y0 - R + r;
+    mreg[r] = (xin && y >= 0 && y < H) ? a.mpre[static_cast<int64_t>(y) * pitch + x] : 0.f;
+  }
+  const bool out_lane = lane >= R + 1 && lane <= 63 - R && xin;
+  float wreg[TY];
+#pragma unroll
+  for (int o = 0; o < TY; ++o) {
+    const int y = y0 + o;
+    wreg[o] = (out_lane && y < H) ? a.wt[static_cast<int64_t>(y) * pitch + x] * scale : 0.f;
+  }
+  // store offset of this lane (out of range for lanes that hold no output)
+  const uint32_t soff = out_lane ? static_cast<uint32_t>(x) * EB : 0x80000000u;
+  auto phys = [nth](int j) {
+    int k = j % nth;
+    return k < 0 ? k + nth : k;
+  };
+  __syncthreads();  // shift table ready
+
+  auto load_slice = [&](int jrel, float(&vv)[NR]) {
+    if (jrel >= count) return;
+    const int kp = phys(jbeg + jrel);
+    const int nx = __builtin_amdgcn_readfirstlane(pnx[kp]);
+    const int ny = __builtin_amdgcn_readfirstlane(pny[kp]);
+    const int c = x - nx;
+    // negative columns wrap to huge offsets and read as 0 like columns >= pitch
+    const uint32_t loff = static_cast<uint32_t>(c) * EB;
+    const int sy0 = y0 - R - ny - 1;
+    const T* plane = bin + static_cast<int64_t>(kp) * sstride;
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      const int sy = sy0 + r;
+      const bool ok = static_cast<unsigned>(sy) < static_cast<unsigned>(H);
+      const T* row = plane + static_cast<int64_t>(ok ? sy : 0) * pitch;
+      vv[r] = Elt<T>::load(row_rsrc(row, ok ? row_bytes : 0u), loff);
+    }
+  };
+  auto process = [&](int jrel, float(&vv)[NR]) {
+    const int kp = phys(jbeg + jrel);
+    const float fx = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, pfx[kp])));
+    const float fy = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, pfy[kp])));
+#pragma unroll
+    for (int r = 0; r < NR; ++r) vv[r] = fmaf(fx, from_left(vv[r]) - vv[r], vv[r]);
+#pragma unroll
+    for (int r = 0; r < NS; ++r) vv[r] = fmaf(fy, vv[r] - vv[r + 1], vv[r + 1]) * mreg[r];
+    float* slot = &ring[jrel % RS][lane][0];
+#pragma unroll
+    for (int o4 = 0; o4 < TY; o4 += 4) {
+      float p4[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int o = o4 + q;
+        float yv = gx[0] * vv[o];
+#pragma unroll
+        for (int l = 1; l < TAPS; ++l) yv = fmaf(gx[l], vv[o + l], yv);
+        float p = gx[R] * yv;
+        float sl = yv, sr = yv;
+#pragma unroll
+        for (int m = 1; m <= R; ++m) {
+          sl = from_left(sl);
+          sr = from_right(sr);
+          p = fmaf(gx[R + m], sl + sr, p);
+        }
+        p4[q] = p;
+      }
+      *reinterpret_cast<float4*>(slot + o4) = make_float4(p4[0], p4[1], p4[2], p4[3]);
+    }
+  };
+  float psum = 0.f, pmax = 0.f;
+  auto emit = [&](int g) {
+    const int krel = WAVES * g - 2 * R + w;
+    if (krel < 0 || krel >= nk) return;
+    const int ko = kbeg + krel;
+    const T* oplane = bout + static_cast<int64_t>(ko) * sstride;
+    int sl[TAPS];
+#pragma unroll
+    for (int l = 0; l < TAPS; ++l) sl[l] = (krel + l) % RS;
+#pragma unroll
+    for (int o4 = 0; o4 < TY; o4 += 4) {
+      float acc[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int l = 0; l < TAPS; ++l) {
+        const float4 r4 = *reinterpret_cast<const float4*>(&ring[sl[l]][lane][o4]);
+        acc[0] = fmaf(gt[l], r4.x, acc[0]);
+        acc[1] = fmaf(gt[l], r4.y, acc[1]);
+        acc[2] = fmaf(gt[l], r4.z, acc[2]);
+        acc[3] = fmaf(gt[l], r4.w, acc[3]);
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int o = o4 + q;
+        const float ov = acc[q] * wreg[o];
+        psum += ov;
+        pmax = fmaxf(pmax, ov);
+        const int y = y0 + o;
+        const bool ok = y < H;
+        const T* row = oplane + static_cast<int64_t>(ok ? y : 0) * pitch;
+        Elt<T>::store(ov, row_rsrc(row, ok ? row_bytes : 0u), soff);
+      }
+    }
+  };
+
+  const int G = (count + WAVES - 1) / WAVES;
+  float vA[NR], vB[NR];
+  load_slice(w, vA);
+  for (int g = 0; g < G; g += 2) {
+    load_slice(WAVES * (g + 1) + w, vB);
+    if (WAVES * g + w < count) process(WAVES * g + w, vA);
+    __syncthreads();
+    emit(g);
+    __syncthreads();
+    if (g + 1 >= G) break;
+    load_slice(WAVES * (g + 2) + w, vA);
+    if (WAVES * (g + 1) + w < count) process(WAVES * (g + 1) + w, vB);
+    __syncthreads();
+    emit(g + 1);
+    __syncthreads();
+  }
+
+  red_s[t] = static_cast<double>(psum);
+  red_m[t] = pmax;
   __syncthreads();
 #pragma unroll
-  for (int st = NT / 2; st > 0; st >>= 1) {
-    if (t < st) {
-      red_s[t] += red_s[t + st];
-      red_m[t] = fmaxf(red_m[t], red_m[t + st]);
+  for (int s = NT / 2; s > 0; s >>= 1) {
+    if (t < s) {
+      red_s[t] += red_s[t + s];
+      red_m[t] = fmaxf(red_m[t], red_m[t + s]);
     }
     __syncthreads();
   }
   if (t == 0) {
-    const double tot = red_s[0];
-    const float m = red_m[0];
-    if (!(tot > 0.0) || !isfinite(tot) || !(m > 0.f)) {
-      dev->status = kStatusDegenerate;  // keep the previous belief (cur unchanged)
-    } else {
-      dev->log_norm += log(tot) - log(static_cast<double>(scale)) - dev->lnsum;
-      dev->lnsum = log(tot);
-      dev->sum = tot;
-      dev->maxval = m;
-      const double sc = 1.0 / static_cast<double>(m);
-      dev->scale = sc > static_cast<double>(FLT_MAX) ? FLT_MAX : static_cast<float>(sc);
-      dev->cur = cur ^ 1;
-    }
-    __hip_atomic_store(&dev->counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    a.partials[2 * blk] = red_s[0];
+    a.partials[2 * blk + 1] = static_cast<double>(red_m[0]);
+    const uint32_t prev = __hip_atomic_fetch_add(&dev->counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    last_flag = (prev == static_cast<uint32_t>(nblk - 1));
   }
+  __syncthreads();
+  if (!last_flag) return;
+  finalize_step<NT>(a, dev, nblk, scale, cur, red_s, red_m);
 }
 
 template <typename T, int R, int TX, int TY, int NT>
@@ -431,14 +720,30 @@ __global__ __launch_bounds__(NT) void step_single(StepArgs a) {
   step_body<T, R, TX, TY, NT>(a, xcd_remap(blockIdx.x, n), n);
 }
 
-// Batch: block_job[2*g] = job, block_job[2*g+1] = block within that job.
 template <typename T, int R, int TX, int TY, int NT>
 __global__ __launch_bounds__(NT) void step_batch(const StepArgs* __restrict__ jobs,
-                                                 const int32_t* __restrict__ block_job, int total) {
+                                                 const int32_t* __restrict__ first, int njobs, int total) {
   const int g = xcd_remap(blockIdx.x, total);
-  const StepArgs& a = jobs[block_job[2 * g]];
+  const int j = find_job(first, njobs, g);
+  const StepArgs& a = jobs[j];
   const int n = a.tiles_x * a.tiles_y * a.chunks;
-  step_body<T, R, TX, TY, NT>(a, block_job[2 * g + 1], n);
+  step_body<T, R, TX, TY, NT>(a, g - first[j], n);
+}
+
+template <typename T, int R, int TY, int WAVES>
+__global__ __launch_bounds__(64 * WAVES) void stream_single(StepArgs a) {
+  const int n = a.tiles_x * a.tiles_y * a.chunks;
+  stream_body<T, R, TY, WAVES>(a, xcd_remap(blockIdx.x, n), n);
+}
+
+template <typename T, int R, int TY, int WAVES>
+__global__ __launch_bounds__(64 * WAVES) void stream_batch(const StepArgs* __restrict__ jobs,
+                                                           const int32_t* __restrict__ first, int njobs, int total) {
+  const int g = xcd_remap(blockIdx.x, total);
+  const int j = find_job(first, njobs, g);
+  const StepArgs& a = jobs[j];
+  const int n = a.tiles_x * a.tiles_y * a.chunks;
+  stream_body<T, R, TY, WAVES>(a, g - first[j], n);
 }
 
 template <typename T, int R, int TX, int TY, int NT>
@@ -449,21 +754,40 @@ hipError_t launch_one(const StepArgs& a, hipStream_t s) {
 }
 
 template <typename T, int R, int TX, int TY, int NT>
-hipError_t launch_many(const StepArgs* jobs, const int32_t* bj, int total, hipStream_t s) {
-  hipLaunchKernelGGL((step_batch<T, R, TX, TY, NT>), dim3(total), dim3(NT), 0, s, jobs, bj, total);
+hipError_t launch_many(const StepArgs* jobs, const int32_t* first, int njobs, int total, hipStream_t s) {
+  hipLaunchKernelGGL((step_batch<T, R, TX, TY, NT>), dim3(total), dim3(NT), 0, s, jobs, first, njobs, total);
   return hipGetLastError();
 }
 
-// Instantiated launch shapes: (TX, TY, NT).
+template <typename T, int R, int TY, int WAVES>
+hipError_t launch_stream(const StepArgs* single, const StepArgs* jobs, const int32_t* first, int njobs, int total,
+                         hipStream_t s) {
+  if (single) {
+    const int n = single->tiles_x * single->tiles_y * single->chunks;
+    hipLaunchKernelGGL((stream_single<T, R, TY, WAVES>), dim3(n), dim3(64 * WAVES), 0, s, *single);
+  } else {
+    hipLaunchKernelGGL((stream_batch<T, R, TY, WAVES>), dim3(total), dim3(64 * WAVES), 0, s, jobs, first, njobs,
+                       total);
+  }
+  return hipGetLastError();
+}
+
+// Instantiated launch shapes.  Tiled kernel: (TX, TY, NT).  Streaming kernel:
+// TX = 0, TY rows per strip, NT = 64 * waves.
 #define MCL_SHAPES(X) X(64, 16, 256) X(32, 16, 128)
+#define MCL_STREAM_SHAPES(X) X(16, 4) X(8, 4) X(12, 4)
 
 template <typename T, int R>
 hipError_t dispatch_shape(int tx, int ty, int nt, const StepArgs* single, const StepArgs* jobs,
-                          const int32_t* bj, int total, hipStream_t s) {
+                          const int32_t* bj, int nj, int total, hipStream_t s) {
+#define MCL_TRY_STREAM(TY_, WV_) \
+  if (tx == 0 && ty == TY_ && nt == 64 * WV_) return launch_stream<T, R, TY_, WV_>(single, jobs, bj, nj, total, s);
+  MCL_STREAM_SHAPES(MCL_TRY_STREAM)
+#undef MCL_TRY_STREAM
 #define MCL_TRY(TX_, TY_, NT_)                                                  \
   if (tx == TX_ && ty == TY_ && nt == NT_)                                      \
     return single ? launch_one<T, R, TX_, TY_, NT_>(*single, s)                 \
-                  : launch_many<T, R, TX_, TY_, NT_>(jobs, bj, total, s);
+                  : launch_many<T, R, TX_, TY_, NT_>(jobs, bj, nj, total, s);
   MCL_SHAPES(MCL_TRY)
 #undef MCL_TRY
   return hipErrorInvalidValue;
@@ -471,22 +795,22 @@ hipError_t dispatch_shape(int tx, int ty, int nt, const StepArgs* single, const 
 
 template <typename T>
 hipError_t dispatch_radius(int radius, int tx, int ty, int nt, const StepArgs* single,
-                           const StepArgs* jobs, const int32_t* bj, int total, hipStream_t s) {
+                           const StepArgs* jobs, const int32_t* bj, int nj, int total, hipStream_t s) {
   switch (radius) {
-    case 1: return dispatch_shape<T, 1>(tx, ty, nt, single, jobs, bj, total, s);
-    case 2: return dispatch_shape<T, 2>(tx, ty, nt, single, jobs, bj, total, s);
-    case 3: return dispatch_shape<T, 3>(tx, ty, nt, single, jobs, bj, total, s);
-    case 4: return dispatch_shape<T, 4>(tx, ty, nt, single, jobs, bj, total, s);
+    case 1: return dispatch_shape<T, 1>(tx, ty, nt, single, jobs, bj, nj, total, s);
+    case 2: return dispatch_shape<T, 2>(tx, ty, nt, single, jobs, bj, nj, total, s);
+    case 3: return dispatch_shape<T, 3>(tx, ty, nt, single, jobs, bj, nj, total, s);
+    case 4: return dispatch_shape<T, 4>(tx, ty, nt, single, jobs, bj, nj, total, s);
     default: return hipErrorInvalidValue;
   }
 }
 
 hipError_t dispatch(int dtype, int radius, int tx, int ty, int nt, const StepArgs* single,
-                    const StepArgs* jobs, const int32_t* bj, int total, hipStream_t s) {
+                    const StepArgs* jobs, const int32_t* bj, int nj, int total, hipStream_t s) {
   switch (dtype) {
-    case 0: return dispatch_radius<float>(radius, tx, ty, nt, single, jobs, bj, total, s);
-    case 1: return dispatch_radius<__bf16>(radius, tx, ty, nt, single, jobs, bj, total, s);
-    case 2: return dispatch_radius<_Float16>(radius, tx, ty, nt, single, jobs, bj, total, s);
+    case 0: return dispatch_radius<float>(radius, tx, ty, nt, single, jobs, bj, nj, total, s);
+    case 1: return dispatch_radius<__bf16>(radius, tx, ty, nt, single, jobs, bj, nj, total, s);
+    case 2: return dispatch_radius<_Float16>(radius, tx, ty, nt, single, jobs, bj, nj, total, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -499,16 +823,20 @@ bool step_config_supported(int dtype, int radius, int tx, int ty, int nt) {
   if (tx == TX_ && ty == TY_ && nt == NT_) return true;
   MCL_SHAPES(MCL_HAS)
 #undef MCL_HAS
+#define MCL_HAS_STREAM(TY_, WV_) \
+  if (tx == 0 && ty == TY_ && nt == 64 * WV_) return true;
+  MCL_STREAM_SHAPES(MCL_HAS_STREAM)
+#undef MCL_HAS_STREAM
   return false;
 }
 
 hipError_t launch_step(int dtype, int radius, int tx, int ty, int nt, const StepArgs& a, hipStream_t s) {
-  return dispatch(dtype, radius, tx, ty, nt, &a, nullptr, nullptr, 0, s);
+  return dispatch(dtype, radius, tx, ty, nt, &a, nullptr, nullptr, 0, 0, s);
 }
 
 hipError_t launch_step_batch(int dtype, int radius, int tx, int ty, int nt, const StepArgs* jobs_dev,
-                             const int32_t* block_job_dev, int32_t total_blocks, hipStream_t s) {
-  return dispatch(dtype, radius, tx, ty, nt, nullptr, jobs_dev, block_job_dev, total_blocks, s);
+                             const int32_t* first_dev, int32_t njobs, int32_t total_blocks, hipStream_t s) {
+  return dispatch(dtype, radius, tx, ty, nt, nullptr, jobs_dev, first_dev, njobs, total_blocks, s);
 }
 
 }  // namespace mcl

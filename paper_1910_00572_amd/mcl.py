@@ -28,7 +28,7 @@ ABI_SYMBOLS = [
     "mcl_last_error", "mcl_map_workspace_bytes", "mcl_map_create", "mcl_map_destroy",
     "mcl_filter_workspace_bytes", "mcl_init_belief", "mcl_filter_destroy", "mcl_step_odometry",
     "mcl_apply_scan", "mcl_normalize", "mcl_read_belief", "mcl_export_belief", "mcl_scan_sqdist",
-    "mcl_get_info", "mcl_step_batch",
+    "mcl_get_info", "mcl_step_batch", "mcl_batch_workspace_bytes",
 ]
 
 
@@ -108,7 +108,9 @@ def load_library(path: str = _LIB_PATH):
     lib.mcl_get_info.restype = c_int
     lib.mcl_get_info.argtypes = [c_void_p, c_int, POINTER(Info)]
     lib.mcl_step_batch.restype = c_int
-    lib.mcl_step_batch.argtypes = [POINTER(c_void_p), c_void_p, c_int32, c_void_p]
+    lib.mcl_step_batch.argtypes = [POINTER(c_void_p), c_void_p, c_int32, c_void_p, c_size_t, c_void_p]
+    lib.mcl_batch_workspace_bytes.restype = c_size_t
+    lib.mcl_batch_workspace_bytes.argtypes = [c_int32]
     _lib = lib
     return lib
 
@@ -274,9 +276,28 @@ def read_belief(f: Filter, want_belief=True):
     return f.read_belief(want_belief)
 
 
-def step_batch(filters, uvw, stream=None):
-    """One odometry step for each filter (serving); uvw: (n, 3) float64."""
+class BatchWorkspace:
+    """Device job table of step_batch for up to `max_filters` filters."""
+
+    def __init__(self, max_filters):
+        import torch
+        lib = load_library()
+        self.max_filters = int(max_filters)
+        n = lib.mcl_batch_workspace_bytes(self.max_filters)
+        if n == 0:
+            raise MclError(EINVAL, "batch size out of range")
+        self.nbytes = n
+        self.tensor = torch.empty(n, dtype=torch.uint8, device="cuda")
+
+
+def step_batch(filters, uvw, workspace: BatchWorkspace, stream=None):
+    """One odometry step for each filter in as few launches as possible (serving).
+
+    uvw: (n, 3) float64 robot-frame increments.  Results are bitwise identical
+    to stepping each filter alone.
+    """
+    assert len(filters) <= workspace.max_filters
     arr = (c_void_p * len(filters))(*[f.handle.value for f in filters])
     u = np.ascontiguousarray(uvw, dtype=np.float64)
-    _check(load_library().mcl_step_batch(arr, u.ctypes.data, len(filters),
-                                         _stream_handle(stream)))
+    _check(load_library().mcl_step_batch(arr, u.ctypes.data, len(filters), c_void_p(workspace.tensor.data_ptr()),
+                                         workspace.nbytes, _stream_handle(stream)))

@@ -1,0 +1,164 @@
+"""Dense scan update on the GPU vs the FP64 oracle (GPU only; through the C ABI).
+
+The squared distance D is an exact integer on both sides (quantised ranges,
+exact MFMA accumulation), so it is compared bit for bit, for BF16 and FP32
+matrix operands.  The posterior is compared with the oracle's log-domain
+update: peak-normalised max-abs error <= 2e-5 for FP32 storage.  That bound
+is derived from the FP32 arithmetic of the update: each stored value is
+exp(L - M*) with L - M* formed from two FP32 logarithms of values near the
+peak (abs. error ~1e-7 each) and c (D - D_ref) with |c (D - D_ref)| of tens
+of nats for the states that matter (relative error 6e-8, abs. ~3e-6), plus
+the FP32 exp (~1e-7): about 5e-6 relative per value, with a factor 4 margin.
+"""
+
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+from gen import bsp_rooms, noisy_scan, random_odometry, range_table, rooms_and_corridors, smooth_trajectory
+from tests.gpu_harness import in_tie_set, make_gpu, needs_gpu, oracle_params, peak_err, say
+
+pytestmark = [pytest.mark.gpu, needs_gpu]
+
+SCAN_PEAK_TOL = 2e-5
+
+
+def _setup(occ, cell, n_dirs, max_range, n_theta, sxy=0.7, sth=0.7, flags=3, theta0=0.0):
+    R = range_table(occ, cell, n_dirs, max_range)
+    m, f = make_gpu(occ, cell, n_theta, sxy, sth, flags=flags, range_table=R, max_range_m=max_range,
+                    theta0=theta0)
+    return R, m, f
+
+
+@pytest.mark.parametrize("f32_ops", [False, True])
+def test_distance_is_exact_small(f32_ops):
+    occ = bsp_rooms(40, 33, seed=31)
+    theta0 = 0.377
+    flags = 3 | (8 if f32_ops else 0)
+    R, m, f = _setup(occ, 0.1, 64, 3.0, 12, flags=flags, theta0=theta0)
+    rng = np.random.default_rng(32)
+    z = rng.uniform(0.0, 3.2, 64).astype(np.float32)
+    say(f"[scan] exact D small f32_ops={f32_ops}")
+    d_gpu = f.scan_sqdist(z).cpu().numpy().astype(np.int64)
+    Rq = O.quantize_ranges(R, 3.0)
+    zq = O.quantize_ranges(z, 3.0)
+    d_ref = O.scan_sqdist(Rq, zq, O.beam_offsets(theta0, 12, 64)).reshape(12, 33, 40)
+    assert np.array_equal(d_gpu, d_ref)
+
+
+def test_distance_is_exact_full_size_sampled():
+    # 512x512 cells, 360 directions, 72 channels: the GEMM shape of the scan workload
+    occ = rooms_and_corridors(512, 512, seed=3)
+    R, m, f = _setup(occ, 0.05, 360, 10.0, 72, sxy=1.0, sth=1.0, theta0=1.234)
+    rng = np.random.default_rng(33)
+    poses, _ = smooth_trajectory(occ, 0.05, 1, seed=4)
+    z = noisy_scan(occ, 0.05, poses[0], 360, 10.0, 0.1, seed=7)
+    say("[scan] exact D full size")
+    d_gpu = f.scan_sqdist(z).cpu().numpy().reshape(72, -1)
+    Rq = O.quantize_ranges(R, 10.0)
+    zq = O.quantize_ranges(z, 10.0)
+    cells = rng.choice(512 * 512, 3000, replace=False)
+    d_ref = O.scan_sqdist(Rq, zq, O.beam_offsets(1.234, 72, 360), rows=cells)
+    assert np.array_equal(d_gpu[:, cells].astype(np.int64), d_ref)
+
+
+@pytest.mark.parametrize("f32_ops", [False, True])
+def test_scan_update_matches_oracle_with_motion(f32_ops):
+    occ = bsp_rooms(64, 56, seed=34)
+    n_theta = 16
+    flags = 3 | (8 if f32_ops else 0)
+    R, m, f = _setup(occ, 0.1, 90, 4.0, n_theta, flags=flags)
+    p = oracle_params(n_theta, 0.1, 0.7, 0.7, flags=3)
+    Rq = O.quantize_ranges(R, 4.0)
+    st = O.init_uniform(occ, n_theta)
+    odo = random_odometry(30, seed=35)
+    free = np.argwhere(occ == 0)
+    rng = np.random.default_rng(36)
+    for t, (u, v, w) in enumerate(odo):
+        f.step_odometry(u, v, w)
+        st = O.step(st, occ, p, u, v, w)
+        if t % 10 == 9:
+            j, i = free[rng.integers(len(free))]
+            z = noisy_scan(occ, 0.1, ((i + 0.5) * 0.1, (j + 0.5) * 0.1, rng.uniform(-3, 3)), 90, 4.0, 0.1,
+                           seed=t)
+            f.apply_scan(z, 0.1)
+            st = O.apply_scan(st, Rq, O.quantize_ranges(z, 4.0), 0.1, 4.0)
+            b, pose, _, ln = f.read_belief()
+            err = peak_err(b, st.B)
+            say(f"[scan] step {t} f32_ops={f32_ops} peak-normalised error {err:.3e} log_norm {ln:.6f} vs {st.log_norm:.6f}")
+            assert err <= SCAN_PEAK_TOL
+            assert in_tie_set(pose.as_tuple(), st.B, 1e-5)
+            assert ln == pytest.approx(st.log_norm, abs=1e-3, rel=1e-6)
+
+
+def test_noise_free_scan_peaks_at_the_true_state():
+    occ = bsp_rooms(48, 40, seed=37)
+    n_theta = 8
+    R, m, f = _setup(occ, 0.1, 72, 3.0, n_theta)
+    Rq = O.quantize_ranges(R, 3.0)
+    s = O.beam_offsets(0.0, n_theta, 72)
+    j, i, k = 17, 23, 5
+    assert occ[j, i] == 0
+    h = 3.0 / 256
+    zq = np.array([Rq[j * 48 + i, (b + s[k]) % 72] for b in range(72)])
+    z = ((zq + 128) * h).astype(np.float32)  # ranges that quantise back to zq exactly
+    assert np.array_equal(O.quantize_ranges(z, 3.0), zq)
+    f.apply_scan(z, 0.05)
+    b, pose, _, _ = f.read_belief()
+    D = O.scan_sqdist(Rq, zq, s).reshape(n_theta, 40, 48)
+    assert D[pose.k, pose.j, pose.i] == 0
+    assert b[k, j, i] == b.max()
+
+
+def test_scan_errors():
+    from paper_1910_00572_amd import mcl
+    occ = bsp_rooms(32, 30, seed=38)
+    _, f = make_gpu(occ, 0.1, 8, 0.5, 0.5)
+    with pytest.raises(mcl.MclError) as ei:
+        f.apply_scan(np.ones(16, np.float32), 0.1)
+    assert ei.value.status == mcl.ESTATE
+    R, m, g = _setup(occ, 0.1, 16, 2.0, 8)
+    with pytest.raises(mcl.MclError) as ei:
+        g.apply_scan(np.ones(15, np.float32), 0.1)
+    assert ei.value.status == mcl.EINVAL
+    with pytest.raises(mcl.MclError) as ei:
+        g.apply_scan(np.ones(16, np.float32), 0.0)
+    assert ei.value.status == mcl.EINVAL
+
+
+def test_full_size_scan_ratios_match_oracle_distances():
+    # 512x512x72 with 360 beams: the posterior ratio of any two states equals
+    # the prior ratio times exp(-c (D_a - D_b)) with D from the oracle's direct
+    # per-beam sum (sampled states, full-size launch shape).
+    occ = rooms_and_corridors(512, 512, seed=3)
+    poses, odo = smooth_trajectory(occ, 0.05, 10, seed=4)
+    R, m, f = _setup(occ, 0.05, 360, 10.0, 72, sxy=1.0, sth=1.0)
+    for u, v, w in odo:
+        f.step_odometry(u, v, w)
+    prior, _, th, _ = f.read_belief()
+    z = noisy_scan(occ, 0.05, poses[-1], 360, 10.0, 0.1, seed=7)
+    f.apply_scan(z, 0.1)
+    post, pose, _, _ = f.read_belief()
+    Rq = O.quantize_ranges(R, 10.0)
+    zq = O.quantize_ranges(z, 10.0)
+    s = O.beam_offsets(th, 72, 360)
+    h = 10.0 / 256
+    c = h * h / (2 * 0.1 ** 2)
+    # reference state: the GPU posterior argmax; samples near it carry mass
+    ref_cell = pose.j * 512 + pose.i
+    rng = np.random.default_rng(39)
+    flat_post = post.reshape(72, -1)
+    flat_prior = prior.reshape(72, -1)
+    cand = np.argwhere(flat_post > flat_post.max() * 1e-3)
+    pick = cand[rng.choice(len(cand), min(300, len(cand)), replace=False)]
+    cells = np.unique(np.concatenate([pick[:, 1], [ref_cell]]))
+    D = O.scan_sqdist(Rq, zq, s, rows=cells)
+    col = {cc: n for n, cc in enumerate(cells)}
+    d_ref = D[pose.k, col[ref_cell]]
+    for k, cell in pick:
+        lhs = math.log(flat_post[k, cell]) - math.log(flat_post[pose.k, ref_cell])
+        rhs = (math.log(flat_prior[k, cell]) - math.log(flat_prior[pose.k, ref_cell])
+               - c * (D[k, col[cell]] - d_ref))
+        assert lhs == pytest.approx(rhs, abs=2e-4)
