@@ -25,6 +25,8 @@
 #include <float.h>
 #include <math.h>
 
+#include <type_traits>
+
 #include "mcl_internal.hpp"
 
 namespace mcl {
@@ -177,7 +179,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int blk, cons
   static_assert(R >= 1 && R <= kMaxRadius, "radius");
   static_assert((NT & (NT - 1)) == 0, "power-of-two workgroup");
 
-  __shared__ __attribute__((aligned(16))) float rawL[WR][SCP];
+  __shared__ __attribute__((aligned(16))) float rawL[WR][SC + 8];
   __shared__ __attribute__((aligned(16))) float sL[SR][SCP];
   __shared__ __attribute__((aligned(16))) float yL[TY][SCP];
   __shared__ int pnx[kMaxTheta], pny[kMaxTheta];
@@ -302,10 +304,8 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int blk, cons
         const int kp = phys(j);
         const float fx = pfx[kp], fy = pfy[kp];
         {
-          // P1: window registers -> LDS, realigned by m so that S column c
-          // reads window columns c (weight fx) and c+1 (weight 1-fx).
-          const int colbase = x0 - RQ - pnx[kp] - 1;
-          const int m = ((colbase % VEC) + VEC) % VEC;
+          // P1: window registers -> LDS as loaded (aligned 16-byte writes,
+          // conflict-free); the misalignment is resolved in P2.
 #pragma unroll
           for (int i = 0; i < IPT1; ++i) {
             const int id = t + i * NT;
@@ -314,39 +314,56 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int blk, cons
               float vals[VEC];
               Store<T>::unpack(pre[i], vals);
 #pragma unroll
-              for (int e = 0; e < VEC; ++e) {
-                const int c = vv * VEC + e - m;
-                if (c >= 0 && c <= SC) rawL[r][c] = vals[e];
-              }
+              for (int e = 0; e < VEC; e += 4)
+                *reinterpret_cast<float4*>(&rawL[r][vv * VEC + e]) =
+                    make_float4(vals[e], vals[e + 1], vals[e + 2], vals[e + 3]);
             }
           }
         }
         __syncthreads();
         if (jrel + 1 < count) issue_loads(j + 1);
 
-        // P2: bilinear weights and pre-blur mask -> S.
+        // P2: bilinear weights and pre-blur mask -> S.  S column c reads window
+        // columns c + m (weight fx) and c + m + 1, m = window misalignment
+        // (uniform): two aligned 16-byte reads per row, then a compile-time
+        // selection for m mod 4.
+        {
+          const int colbase = x0 - RQ - pnx[kp] - 1;
+          const int m = ((colbase % VEC) + VEC) % VEC;
+          const int mh = m >> 2, ml = m & 3;
+          auto p2 = [&](auto mlc) {
+            constexpr int ML = decltype(mlc)::value;
 #pragma unroll
-        for (int i = 0; i < IPT2; ++i) {
-          const int id = t + i * NT;
-          if (id < NS) {
-            const int srp = id / NQ, q = id % NQ;
-            float xr[3][4];
+            for (int i = 0; i < IPT2; ++i) {
+              const int id = t + i * NT;
+              if (id < NS) {
+                const int srp = id / NQ, q = id % NQ;
+                const int c0 = 4 * (q + mh);
+                float xr[3][4];
 #pragma unroll
-            for (int rr = 0; rr < 3; ++rr) {
-              const float4 w4 = *reinterpret_cast<const float4*>(&rawL[2 * srp + rr][4 * q]);
-              const float w5 = rawL[2 * srp + rr][4 * q + 4];
-              const float wv[5] = {w4.x, w4.y, w4.z, w4.w, w5};
+                for (int rr = 0; rr < 3; ++rr) {
+                  const float4 a4 = *reinterpret_cast<const float4*>(&rawL[2 * srp + rr][c0]);
+                  const float4 b4 = *reinterpret_cast<const float4*>(&rawL[2 * srp + rr][c0 + 4]);
+                  const float wv[8] = {a4.x, a4.y, a4.z, a4.w, b4.x, b4.y, b4.z, b4.w};
 #pragma unroll
-              for (int e = 0; e < 4; ++e) xr[rr][e] = fmaf(fx, wv[e] - wv[e + 1], wv[e + 1]);
+                  for (int e = 0; e < 4; ++e) xr[rr][e] = fmaf(fx, wv[ML + e] - wv[ML + e + 1], wv[ML + e + 1]);
+                }
+#pragma unroll
+                for (int sidx = 0; sidx < 2; ++sidx) {
+                  float sv[4];
+#pragma unroll
+                  for (int e = 0; e < 4; ++e)
+                    sv[e] = fmaf(fy, xr[sidx][e] - xr[sidx + 1][e], xr[sidx + 1][e]) * mreg[i][sidx][e];
+                  *reinterpret_cast<float4*>(&sL[2 * srp + sidx][4 * q]) = make_float4(sv[0], sv[1], sv[2], sv[3]);
+                }
+              }
             }
-#pragma unroll
-            for (int s = 0; s < 2; ++s) {
-              float sv[4];
-#pragma unroll
-              for (int e = 0; e < 4; ++e)
-                sv[e] = fmaf(fy, xr[s][e] - xr[s + 1][e], xr[s + 1][e]) * mreg[i][s][e];
-              *reinterpret_cast<float4*>(&sL[2 * srp + s][4 * q]) = make_float4(sv[0], sv[1], sv[2], sv[3]);
-            }
+          };
+          switch (ml) {
+            case 0: p2(std::integral_constant<int, 0>()); break;
+            case 1: p2(std::integral_constant<int, 1>()); break;
+            case 2: p2(std::integral_constant<int, 2>()); break;
+            default: p2(std::integral_constant<int, 3>()); break;
           }
         }
         __syncthreads();
@@ -469,11 +486,12 @@ struct Elt;
 template <>
 struct Elt<float> {
   static constexpr int BYTES = 4;
+  // the b32 buffer builtins move raw 32-bit words: bit-cast, never convert
   __device__ static inline float load(__amdgpu_buffer_rsrc_t r, uint32_t off) {
-    return __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0);
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
   }
   __device__ static inline void store(float v, __amdgpu_buffer_rsrc_t r, uint32_t off) {
-    __builtin_amdgcn_raw_buffer_store_b32(v, r, off, 0, 0);
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, off, 0, 0);
   }
 };
 template <>

@@ -84,13 +84,23 @@ def test_scan_update_matches_oracle_with_motion(f32_ops):
             z = noisy_scan(occ, 0.1, ((i + 0.5) * 0.1, (j + 0.5) * 0.1, rng.uniform(-3, 3)), 90, 4.0, 0.1,
                            seed=t)
             f.apply_scan(z, 0.1)
+            prior = st.B
             st = O.apply_scan(st, Rq, O.quantize_ranges(z, 4.0), 0.1, 4.0)
             b, pose, _, ln = f.read_belief()
             err = peak_err(b, st.B)
-            say(f"[scan] step {t} f32_ops={f32_ops} peak-normalised error {err:.3e} log_norm {ln:.6f} vs {st.log_norm:.6f}")
+            # The log-normaliser of a scan is ln sum_q prior_q P(z|q); when the
+            # posterior is carried by a state whose prior is p_rel of the prior
+            # peak, FP32 storage (peak ~1) holds that prior to a relative
+            # precision of 2^-149 / p_rel once p_rel is below 2^-126 (denormal
+            # range), so the tolerance on ln grows by that much.
+            kq = np.unravel_index(int(np.argmax(st.B)), st.B.shape)
+            p_rel = prior[kq] / prior.max()
+            tol = 1e-5 + 1e-6 * abs(st.log_norm) + (4 * 2.0 ** -149 / p_rel if p_rel < 2.0 ** -126 else 0.0)
+            say(f"[scan] step {t} f32_ops={f32_ops} peak-normalised error {err:.3e} log_norm {ln:.6f} vs "
+                f"{st.log_norm:.6f} (prior at posterior argmax {p_rel:.3e} of peak, tol {tol:.2e})")
             assert err <= SCAN_PEAK_TOL
             assert in_tie_set(pose.as_tuple(), st.B, 1e-5)
-            assert ln == pytest.approx(st.log_norm, abs=1e-3, rel=1e-6)
+            assert abs(ln - st.log_norm) <= tol
 
 
 def test_noise_free_scan_peaks_at_the_true_state():
