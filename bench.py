@@ -185,9 +185,13 @@ def bench_scan(n_scans):
 
 
 def bench_serving(n_requests, seed=8, capacity=None):
-    """Poisson stream of mixed filters (grid 128..1024, 36/72 bins, FP32/BF16, scans on half)."""
+    """Poisson stream of mixed filters (grid 128..1024, 36/72 bins, FP32/BF16, scans on half).
+
+    Every request follows its own seeded smooth trajectory through its map;
+    half of them receive a 360-beam scan from the true pose every 10 steps.
+    """
     import torch
-    from gen import noisy_scan, random_odometry, range_table, rooms_and_corridors
+    from gen import noisy_scan, range_table, rooms_and_corridors, smooth_trajectory
     from paper_1910_00572_amd import mcl
     from paper_1910_00572_amd.serve import Request, Server
     rng = np.random.default_rng(seed)
@@ -204,14 +208,11 @@ def bench_serving(n_requests, seed=8, capacity=None):
         n_theta = int(rng.choice([36, 72]))
         storage = str(rng.choice(["f32", "bf16"]))
         steps = int(rng.integers(50, 501))
-        odo = random_odometry(steps, seed=1000 + rid, max_step_m=0.1)
+        poses, odo = smooth_trajectory(occs[g], 0.05, steps, seed=1000 + rid)
         scans = {}
         if rid % 2 == 0:
-            free = np.argwhere(occs[g] == 0)
             for t in range(9, steps, 10):
-                j, i = free[rng.integers(len(free))]
-                scans[t] = noisy_scan(occs[g], 0.05, ((i + 0.5) * 0.05, (j + 0.5) * 0.05, rng.uniform(-3, 3)),
-                                      360, 10.0, 0.1, seed=rid * 1000 + t)
+                scans[t] = noisy_scan(occs[g], 0.05, poses[t + 1], 360, 10.0, 0.1, seed=rid * 1000 + t)
         total += g * g * n_theta * steps
         reqs.append(Request(rid, 0.0, g, n_theta, storage, odo, scans))
     cap = capacity or 5e11

@@ -114,7 +114,8 @@ struct mcl_map_s {
 };
 
 struct StepShape {
-  int tx = 0, ty = 16, nt = 256, chunks = 1, chunk_len = 1, tiles_x = 1, tiles_y = 1;
+  KernelShape k;
+  int chunks = 1, chunk_len = 1, tiles_x = 1, tiles_y = 1, strip = 0;
   int blocks() const { return tiles_x * tiles_y * chunks; }
 };
 
@@ -148,35 +149,44 @@ constexpr int kReduceBlocks = 1024;
 
 // Launch shape of the step kernel.  Measured on MI355X: the tiled kernel
 // (64 x 16 tiles, 256 threads) is faster once a map has at least 512 tiles
-// (1024^2: 387 us FP32 / 363 us BF16 at 128 bins, against 454 / 396 for the
-// streaming kernel); on smaller maps the streaming kernel with 8-row strips
-// keeps more workgroups busy (512^2 x 72: 78.6 us against 86.3).
-// MCL_STEP_SHAPE="tx,ty,nt[,chunks]" overrides the choice (tx = 0: streaming).
-StepShape choose_shape(int W, int H, int T, int R) {
+// (1024^2 x 128: 390 us FP32 / 367 us BF16, against 411 / 381 for the best
+// streaming shapes); on smaller maps the streaming kernel with 8-row strips
+// keeps more workgroups busy (512^2 x 72 FP32: 68 us against 87).
+// MCL_STEP_SHAPE="tx,ty,nt[,chunks]" overrides the choice (tx = 0:
+// streaming; chunks = 0: automatic).
+// The streaming kernel addresses one heading plane with 32-bit buffer offsets
+// whose out-of-grid markers start at 2^30, so a plane must stay below 1 GiB.
+bool stream_plane_ok(int W, int H, size_t eb) {
+  const size_t pitch = (static_cast<size_t>(W) + kRowAlign - 1) / kRowAlign * kRowAlign;
+  return pitch * static_cast<size_t>(H) * eb < (static_cast<size_t>(1) << 30);
+}
+
+StepShape choose_shape(int W, int H, int T, int R, size_t eb) {
   StepShape s;
   const int tiled_tiles = ((W + 63) / 64) * ((H + 15) / 16);
   int sh[4] = {64, 16, 256, 0};
-  if (tiled_tiles < 512) {
+  if (tiled_tiles < 512 && stream_plane_ok(W, H, eb)) {
     sh[0] = 0;
     sh[1] = 8;
     sh[2] = 256;
     sh[3] = 1;
   }
   if (const char* env = getenv("MCL_STEP_SHAPE")) {
-    int a = 0, b = 0, c = 0, d = 0;
-    if (sscanf(env, "%d,%d,%d,%d", &a, &b, &c, &d) >= 3) {
-      sh[0] = a;
-      sh[1] = b;
-      sh[2] = c;
-      sh[3] = d;
-    }
+    int v[4] = {0, 0, 0, 0};
+    if (sscanf(env, "%d,%d,%d,%d", &v[0], &v[1], &v[2], &v[3]) >= 3)
+      for (int i = 0; i < 4; ++i) sh[i] = v[i];
   }
-  s.tx = sh[0];
-  s.ty = sh[1];
-  s.nt = sh[2];
-  const int strip = s.tx > 0 ? s.tx : 63 - 2 * R;
+  s.k.tx = sh[0];
+  s.k.ty = sh[1];
+  s.k.nt = sh[2];
+  // streaming kernel: 32-byte aligned strips unless MCL_STREAM_ALIGN says otherwise
+  int align = kStreamAlignBytes;
+  if (const char* env = getenv("MCL_STREAM_ALIGN")) align = atoi(env);
+  s.strip = stream_strip_width(R, static_cast<int>(eb), align);
+  if (s.strip <= 0) s.strip = 63 - 2 * R;
+  const int strip = s.k.tx > 0 ? s.k.tx : s.strip;
   s.tiles_x = (W + strip - 1) / strip;
-  s.tiles_y = (H + s.ty - 1) / s.ty;
+  s.tiles_y = (H + s.k.ty - 1) / s.k.ty;
   const int tiles = s.tiles_x * s.tiles_y;
   int chunks = sh[3];
   if (chunks <= 0) {
@@ -208,6 +218,7 @@ StepArgs make_step_args(mcl_filter f) {
   a.tiles_y = f->shape.tiles_y;
   a.chunks = f->shape.chunks;
   a.chunk_len = f->shape.chunk_len;
+  a.strip = f->shape.strip;
   a.sstride = f->sstride;
   a.dtheta = 2.0 * M_PI / f->T;
   for (int i = 0; i < kMaxTaps; ++i) {
@@ -249,7 +260,7 @@ size_t carve_filter(mcl_filter f, void* ws, const mcl_map m, const mcl_params* p
   void* b1 = c.take(n * eb);
   float* staging = static_cast<float*>(c.take(static_cast<size_t>(m->W) * m->H * sizeof(float)));
   const int R = std::max(1, std::max(m->rxy, resolve_radius(p->sigma_theta_bins, p->radius_theta)));
-  const StepShape sh = choose_shape(m->W, m->H, p->n_theta, R);
+  const StepShape sh = choose_shape(m->W, m->H, p->n_theta, R, eb);
   const int np = std::max(sh.blocks(), std::max(kReduceBlocks, kScanMaxBlocks(m->W, m->H, m->pitch)));
   double* partials = static_cast<double*>(c.take(static_cast<size_t>(np) * 3 * sizeof(double)));
   FilterDev* dev = static_cast<FilterDev*>(c.take(sizeof(FilterDev)));
@@ -395,7 +406,8 @@ mcl_status mcl_init_belief(mcl_map map, const mcl_params* p, void* ws, size_t ws
   for (int m = -map->rxy; m <= map->rxy; ++m) f->gxy[f->radius + m] = static_cast<float>(g[m + map->rxy]);
   gaussian_taps(f->sigma_th, f->rth, g);
   for (int m = -f->rth; m <= f->rth; ++m) f->gth[f->radius + m] = static_cast<float>(g[m + f->rth]);
-  if (!step_config_supported(f->dtype, f->radius, f->shape.tx, f->shape.ty, f->shape.nt)) {
+  if (!step_config_supported(f->dtype, f->radius, f->shape.k) ||
+      (f->shape.k.tx == 0 && !stream_plane_ok(map->W, map->H, dtype_bytes(f->dtype)))) {
     delete f;
     return fail(MCL_EINVAL, "no kernel for this storage/radius/shape");
   }
@@ -460,7 +472,7 @@ mcl_status mcl_step_odometry(mcl_filter f, double u, double v, double w) {
     f->theta += w;
     ++f->steps;
   }
-  HIP_TRY(launch_step(f->dtype, f->radius, f->shape.tx, f->shape.ty, f->shape.nt, a, f->stream), "step launch");
+  HIP_TRY(launch_step(f->dtype, f->radius, f->shape.k, a, f->stream), "step launch");
   return MCL_OK;
 }
 
@@ -546,8 +558,8 @@ mcl_status mcl_get_info(mcl_filter f, int sync, mcl_info* out) {
   out->pitch = f->map->pitch;
   out->storage = f->dtype;
   out->radius = f->radius;
-  out->tile_x = f->shape.tx;
-  out->tile_y = f->shape.ty;
+  out->tile_x = f->shape.k.tx;
+  out->tile_y = f->shape.k.ty;
   out->theta_chunks = f->shape.chunks;
   out->workgroups = f->shape.blocks();
   out->steps = f->steps;
@@ -636,7 +648,8 @@ mcl_status mcl_step_batch(mcl_filter* const filters, const double* uvw, int32_t 
   // gate does not fire takes no launch.
   struct Job {
     StepArgs a;
-    int dtype, radius, tx, ty, nt;
+    int dtype, radius;
+    KernelShape k;
   };
   std::vector<Job> jobs;
   jobs.reserve(n);
@@ -667,31 +680,31 @@ mcl_status mcl_step_batch(mcl_filter* const filters, const double* uvw, int32_t 
       f->theta += w;
       ++f->steps;
     }
-    jobs.push_back(Job{a, f->dtype, f->radius, f->shape.tx, f->shape.ty, f->shape.nt});
+    jobs.push_back(Job{a, f->dtype, f->radius, f->shape.k});
   }
   if (jobs.empty()) return MCL_OK;
   auto same = [](const Job& x, const Job& y) {
-    return x.dtype == y.dtype && x.radius == y.radius && x.tx == y.tx && x.ty == y.ty && x.nt == y.nt;
+    return x.dtype == y.dtype && x.radius == y.radius && x.k == y.k;
   };
   auto less = [](const Job& x, const Job& y) {
     if (x.dtype != y.dtype) return x.dtype < y.dtype;
     if (x.radius != y.radius) return x.radius < y.radius;
-    if (x.tx != y.tx) return x.tx < y.tx;
-    if (x.ty != y.ty) return x.ty < y.ty;
-    return x.nt < y.nt;
+    return x.k < y.k;
   };
   std::stable_sort(jobs.begin(), jobs.end(), less);
   // per group: its jobs, then njobs+1 first-block offsets relative to the group
   std::vector<StepArgs> args;
   std::vector<int32_t> first;
   struct Group {
-    int dtype, radius, tx, ty, nt, job0, first0, njobs, blocks;
+    int dtype, radius;
+    KernelShape k;
+    int job0, first0, njobs, blocks;
   };
   std::vector<Group> groups;
   for (size_t i = 0; i < jobs.size(); ++i) {
     if (i == 0 || !same(jobs[i], jobs[i - 1])) {
       if (!groups.empty()) first.push_back(groups.back().blocks);
-      groups.push_back(Group{jobs[i].dtype, jobs[i].radius, jobs[i].tx, jobs[i].ty, jobs[i].nt,
+      groups.push_back(Group{jobs[i].dtype, jobs[i].radius, jobs[i].k,
                              static_cast<int>(args.size()), static_cast<int>(first.size()), 0, 0});
     }
     Group& g = groups.back();
@@ -709,8 +722,7 @@ mcl_status mcl_step_batch(mcl_filter* const filters, const double* uvw, int32_t 
   HIP_TRY(hipMemcpyAsync(first_dev, first.data(), first.size() * sizeof(int32_t), hipMemcpyHostToDevice, s),
           "batch offsets upload");
   for (const Group& g : groups)
-    HIP_TRY(launch_step_batch(g.dtype, g.radius, g.tx, g.ty, g.nt, args_dev + g.job0, first_dev + g.first0, g.njobs,
-                              g.blocks, s),
+    HIP_TRY(launch_step_batch(g.dtype, g.radius, g.k, args_dev + g.job0, first_dev + g.first0, g.njobs, g.blocks, s),
             "batch launch");
   return MCL_OK;
 }

@@ -42,6 +42,7 @@ struct StepArgs {
   FilterDev* dev;
   int32_t W, H, pitch, n_theta;
   int32_t tiles_x, tiles_y, chunks, chunk_len;
+  int32_t strip;              // streaming kernel: output columns per strip
   int64_t sstride;            // elements per heading slice (H * pitch)
   double u_cells, v_cells;    // odometry in cells, robot frame
   double theta_prev, dtheta;  // heading offset before the step, 2 pi / n_theta
@@ -84,12 +85,34 @@ struct Carver {
 
 // ---- launchers (defined in the .hip files) -----------------------------------
 // Return hipSuccess or the launch error.
-hipError_t launch_step(int dtype, int radius, int tx, int ty, int nt, const StepArgs& a,
-                       hipStream_t s);
+// Output columns per strip of the streaming kernel.  Lanes R+1 .. 63-R can
+// hold outputs; the strip is trimmed to a multiple of `align_bytes` of
+// storage so that, with strips starting at multiples of the strip width,
+// every output row store covers whole aligned segments and no two strips
+// write into the same segment.
+constexpr int stream_strip_width(int R, int elt_bytes, int align_bytes) {
+  const int al = align_bytes > elt_bytes ? align_bytes / elt_bytes : 1;
+  return ((63 - 2 * R) / al) * al;
+}
+constexpr int kStreamAlignBytes = 32;
+
+// Launch shape of the step kernel.  tx > 0: tiled kernel with tx x ty tiles
+// and nt threads.  tx == 0: streaming kernel with ty-row strips and nt / 64
+// waves.
+struct KernelShape {
+  int tx = 64, ty = 16, nt = 256;
+  bool operator==(const KernelShape& o) const { return tx == o.tx && ty == o.ty && nt == o.nt; }
+  bool operator<(const KernelShape& o) const {
+    if (tx != o.tx) return tx < o.tx;
+    if (ty != o.ty) return ty < o.ty;
+    return nt < o.nt;
+  }
+};
+hipError_t launch_step(int dtype, int radius, const KernelShape& k, const StepArgs& a, hipStream_t s);
 // jobs_dev[0..njobs) with first_dev[j] = first workgroup of job j (first_dev[njobs] = total).
-hipError_t launch_step_batch(int dtype, int radius, int tx, int ty, int nt, const StepArgs* jobs_dev,
+hipError_t launch_step_batch(int dtype, int radius, const KernelShape& k, const StepArgs* jobs_dev,
                              const int32_t* first_dev, int32_t njobs, int32_t total_blocks, hipStream_t s);
-bool step_config_supported(int dtype, int radius, int tx, int ty, int nt);
+bool step_config_supported(int dtype, int radius, const KernelShape& k);
 
 hipError_t launch_map_setup(const uint8_t* occ_dev, int W, int H, int pitch, const double* gxy,
                             int rxy, double gth_sum, uint32_t flags, uint8_t* free8, float* mpre,

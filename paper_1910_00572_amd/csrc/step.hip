@@ -467,18 +467,18 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int blk, cons
 // the TY + 2R + 1 source rows of a channel through registers: the bilinear
 // x neighbour comes from the adjacent lane (DPP wave shift), the y
 // interpolation, mask and y blur run down a register window, and the x blur
-// uses DPP shifts of the y-blurred rows.  Lanes R+1 .. 63-R hold valid
-// outputs (63 - 2R columns per strip).  The waves of a workgroup take
-// consecutive channels; the theta blur reads a ring of 2R + WAVES channel
-// results in LDS (layout [slot][lane][row], 16-byte reads of four rows),
-// with two barriers per group of WAVES channels.  The next group's source
-// rows are loaded while the current group is computed.
+// uses DPP shifts of the y-blurred rows.  Lanes R+1 .. R+strip hold the
+// strip's outputs (strip <= 63 - 2R, a multiple of 32 bytes of storage, so
+// strips never share a 32-byte segment of an output row).  The waves of a
+// workgroup take consecutive channels; the theta blur reads a ring of
+// 2R + 2 WAVES channel results in LDS (layout [slot][lane][row], 16-byte
+// reads of four rows), with one barrier per group of WAVES channels.  The
+// next group's source rows are loaded while the current group is computed.
 //
-// Rows are read and written through raw buffer descriptors built per row on
-// the scalar unit: the lane offset is the column, a row outside the grid gets
-// an empty descriptor, and the hardware returns 0 for (and drops stores to)
-// out-of-range offsets, so no per-row vector address arithmetic or branch is
-// needed.
+// Rows are read and written through one raw buffer descriptor per heading
+// plane; a row or column outside the grid gets an out-of-range offset, and
+// the hardware returns 0 for (and drops stores to) out-of-range offsets, so
+// the borders need no branch.
 constexpr int kRsrcWord3 = 0x00020000;  // raw buffer, 32-bit data (gfx9 family)
 
 template <typename T>
@@ -515,10 +515,18 @@ struct Elt<_Float16> {
   }
 };
 
-__device__ inline __amdgpu_buffer_rsrc_t row_rsrc(const void* row, uint32_t bytes) {
-  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(row), static_cast<short>(0), static_cast<int>(bytes),
+__device__ inline __amdgpu_buffer_rsrc_t buf_rsrc(const void* base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), static_cast<short>(0), static_cast<int>(bytes),
                                            kRsrcWord3);
 }
+
+// Byte offsets into one heading plane (H * pitch elements, below 1 GiB, one
+// descriptor): a row part below 2^30 for rows inside the grid and 2^30 for
+// rows outside, plus a column part below 2^30 for columns inside the row and
+// 2^31 outside.  The sum stays below 2^32 and is out of range (the load
+// returns 0, the store is dropped) exactly when the row or the column is.
+constexpr uint32_t kRowOut = 1u << 30;
+constexpr uint32_t kColOut = 1u << 31;
 
 // lane i receives lane i-1 / i+1; lanes without a source receive 0
 __device__ inline float from_left(float v) {
@@ -531,10 +539,11 @@ __device__ inline float from_right(float v) {
 template <typename T, int R, int TY, int WAVES>
 __device__ __forceinline__ void stream_body(const StepArgs& a, const int blk, const int nblk) {
   constexpr int NT = 64 * WAVES;
-  constexpr int TXW = 63 - 2 * R;  // valid output columns per strip
   constexpr int NS = TY + 2 * R;   // S rows
   constexpr int NR = NS + 1;       // source rows
-  constexpr int RS = 2 * R + WAVES;
+  // ring slots: a group's emit reads 2R + WAVES channels and the next group's
+  // process writes WAVES more, so one barrier per group suffices
+  constexpr int RS = 2 * R + 2 * WAVES;
   constexpr int TAPS = 2 * R + 1;
   constexpr int LP = TY + 4;       // ring lane pitch (floats): conflict-free 16-byte accesses
   constexpr int EB = Elt<T>::BYTES;
@@ -553,10 +562,12 @@ __device__ __forceinline__ void stream_body(const StepArgs& a, const int blk, co
   const int H = a.H, pitch = a.pitch, nth = a.n_theta;
   const int64_t sstride = a.sstride;
   const uint32_t row_bytes = static_cast<uint32_t>(pitch) * EB;
+  const uint32_t plane_bytes = static_cast<uint32_t>(sstride) * EB;  // < 2^30 (host-checked)
   const int tiles_x = a.tiles_x;
   const int ntile = tiles_x * a.tiles_y;
   const int chunk = blk / ntile, tile = blk % ntile;
-  const int xb = (tile % tiles_x) * TXW - (R + 1);
+  const int strip = a.strip;
+  const int xb = (tile % tiles_x) * strip - (R + 1);
   const int y0 = (tile / tiles_x) * TY;
   const int x = xb + lane;
   const int kbeg = chunk * a.chunk_len;
@@ -595,7 +606,7 @@ __device__ __forceinline__ void stream_body(const StepArgs& a, const int blk, co
     const int y = y0 - R + r;
     mreg[r] = (xin && y >= 0 && y < H) ? a.mpre[static_cast<int64_t>(y) * pitch + x] : 0.f;
   }
-  const bool out_lane = lane >= R + 1 && lane <= 63 - R && xin;
+  const bool out_lane = lane >= R + 1 && lane <= R + strip && xin;
   float wreg[TY];
 #pragma unroll
   for (int o = 0; o < TY; ++o) {
@@ -603,35 +614,50 @@ __device__ __forceinline__ void stream_body(const StepArgs& a, const int blk, co
     wreg[o] = (out_lane && y < H) ? a.wt[static_cast<int64_t>(y) * pitch + x] * scale : 0.f;
   }
   // store offset of this lane (out of range for lanes that hold no output)
-  const uint32_t soff = out_lane ? static_cast<uint32_t>(x) * EB : 0x80000000u;
+  const uint32_t soff = out_lane ? static_cast<uint32_t>(x) * EB : kColOut;
   auto phys = [nth](int j) {
     int k = j % nth;
     return k < 0 ? k + nth : k;
   };
   __syncthreads();  // shift table ready
 
-  auto load_slice = [&](int jrel, float(&vv)[NR]) {
-    if (jrel >= count) return;
-    const int kp = phys(jbeg + jrel);
+  // Source rows of channel jrel and its fractional shift (read here, one
+  // group ahead, so that process() starts without an LDS round trip).
+  //
+  // The loop below has no data-dependent branch around a memory operation:
+  // channels past the end of the chunk load through empty descriptors (the
+  // hardware returns zeros without a memory access) and outputs outside the
+  // chunk store through empty descriptors.  With straight-line control flow
+  // the compiler's wait-counter tracking stays exact across iterations, so
+  // the next group's loads stay in flight while the current group computes
+  // (a branch here makes it wait for every outstanding load and store).
+  struct Slice {
+    float v[NR];
+    float fx, fy;
+  };
+  auto load_slice = [&](int jrel, Slice& sl) {
+    const bool live = jrel < count;
+    const int kp = phys(jbeg + (live ? jrel : 0));
     const int nx = __builtin_amdgcn_readfirstlane(pnx[kp]);
     const int ny = __builtin_amdgcn_readfirstlane(pny[kp]);
+    sl.fx = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, pfx[kp])));
+    sl.fy = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, pfy[kp])));
     const int c = x - nx;
-    // negative columns wrap to huge offsets and read as 0 like columns >= pitch
-    const uint32_t loff = static_cast<uint32_t>(c) * EB;
+    const uint32_t loff = static_cast<unsigned>(c) < static_cast<unsigned>(pitch) ? static_cast<uint32_t>(c) * EB
+                                                                                   : kColOut;
     const int sy0 = y0 - R - ny - 1;
-    const T* plane = bin + static_cast<int64_t>(kp) * sstride;
+    const __amdgpu_buffer_rsrc_t rs = buf_rsrc(bin + static_cast<int64_t>(kp) * sstride, live ? plane_bytes : 0u);
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
       const int sy = sy0 + r;
-      const bool ok = static_cast<unsigned>(sy) < static_cast<unsigned>(H);
-      const T* row = plane + static_cast<int64_t>(ok ? sy : 0) * pitch;
-      vv[r] = Elt<T>::load(row_rsrc(row, ok ? row_bytes : 0u), loff);
+      const uint32_t roff = static_cast<unsigned>(sy) < static_cast<unsigned>(H) ? static_cast<uint32_t>(sy) * row_bytes
+                                                                                 : kRowOut;
+      sl.v[r] = Elt<T>::load(rs, loff + roff);
     }
   };
-  auto process = [&](int jrel, float(&vv)[NR]) {
-    const int kp = phys(jbeg + jrel);
-    const float fx = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, pfx[kp])));
-    const float fy = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, pfy[kp])));
+  auto process = [&](int jrel, Slice& sl) {
+    float(&vv)[NR] = sl.v;
+    const float fx = sl.fx, fy = sl.fy;
 #pragma unroll
     for (int r = 0; r < NR; ++r) vv[r] = fmaf(fx, from_left(vv[r]) - vv[r], vv[r]);
 #pragma unroll
@@ -647,12 +673,12 @@ __device__ __forceinline__ void stream_body(const StepArgs& a, const int blk, co
 #pragma unroll
         for (int l = 1; l < TAPS; ++l) yv = fmaf(gx[l], vv[o + l], yv);
         float p = gx[R] * yv;
-        float sl = yv, sr = yv;
+        float dl = yv, dr = yv;
 #pragma unroll
         for (int m = 1; m <= R; ++m) {
-          sl = from_left(sl);
-          sr = from_right(sr);
-          p = fmaf(gx[R + m], sl + sr, p);
+          dl = from_left(dl);
+          dr = from_right(dr);
+          p = fmaf(gx[R + m], dl + dr, p);
         }
         p4[q] = p;
       }
@@ -660,54 +686,72 @@ __device__ __forceinline__ void stream_body(const StepArgs& a, const int blk, co
     }
   };
   float psum = 0.f, pmax = 0.f;
+  // Theta blur of one channel.  All ring reads of a batch of rows are issued
+  // before the first use (the scheduling barrier keeps the compiler from
+  // interleaving them with the dependent FMAs), so a batch costs one LDS
+  // round trip instead of one per tap.
+  constexpr int RB = 4;
   auto emit = [&](int g) {
     const int krel = WAVES * g - 2 * R + w;
-    if (krel < 0 || krel >= nk) return;
-    const int ko = kbeg + krel;
-    const T* oplane = bout + static_cast<int64_t>(ko) * sstride;
-    int sl[TAPS];
+    const bool live = krel >= 0 && krel < nk;
+    const int ko = kbeg + (live ? krel : 0);
+    const __amdgpu_buffer_rsrc_t rs = buf_rsrc(bout + static_cast<int64_t>(ko) * sstride, live ? plane_bytes : 0u);
+    int slot[TAPS];
 #pragma unroll
-    for (int l = 0; l < TAPS; ++l) sl[l] = (krel + l) % RS;
+    for (int l = 0; l < TAPS; ++l) slot[l] = (krel + l) % RS;
 #pragma unroll
-    for (int o4 = 0; o4 < TY; o4 += 4) {
-      float acc[4] = {0.f, 0.f, 0.f, 0.f};
+    for (int ob = 0; ob < TY; ob += RB) {
+      float4 rv[RB / 4][TAPS];
 #pragma unroll
-      for (int l = 0; l < TAPS; ++l) {
-        const float4 r4 = *reinterpret_cast<const float4*>(&ring[sl[l]][lane][o4]);
-        acc[0] = fmaf(gt[l], r4.x, acc[0]);
-        acc[1] = fmaf(gt[l], r4.y, acc[1]);
-        acc[2] = fmaf(gt[l], r4.z, acc[2]);
-        acc[3] = fmaf(gt[l], r4.w, acc[3]);
-      }
+      for (int q = 0; q < RB / 4; ++q)
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int o = o4 + q;
-        const float ov = acc[q] * wreg[o];
-        psum += ov;
-        pmax = fmaxf(pmax, ov);
-        const int y = y0 + o;
-        const bool ok = y < H;
-        const T* row = oplane + static_cast<int64_t>(ok ? y : 0) * pitch;
-        Elt<T>::store(ov, row_rsrc(row, ok ? row_bytes : 0u), soff);
+        for (int l = 0; l < TAPS; ++l)
+          rv[q][l] = *reinterpret_cast<const float4*>(&ring[slot[l]][lane][ob + 4 * q]);
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int q = 0; q < RB / 4; ++q) {
+        float acc[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int l = 0; l < TAPS; ++l) {
+          acc[0] = fmaf(gt[l], rv[q][l].x, acc[0]);
+          acc[1] = fmaf(gt[l], rv[q][l].y, acc[1]);
+          acc[2] = fmaf(gt[l], rv[q][l].z, acc[2]);
+          acc[3] = fmaf(gt[l], rv[q][l].w, acc[3]);
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int o = ob + 4 * q + e;
+          const float ov = acc[e] * wreg[o];
+          const float ovk = live ? ov : 0.f;
+          psum += ovk;
+          pmax = fmaxf(pmax, ovk);
+          const int y = y0 + o;
+          const uint32_t roff = y < H ? static_cast<uint32_t>(y) * row_bytes : kRowOut;
+          Elt<T>::store(ov, rs, soff + roff);
+        }
       }
     }
   };
 
-  const int G = (count + WAVES - 1) / WAVES;
-  float vA[NR], vB[NR];
-  load_slice(w, vA);
+  // Two-slice software pipeline over an even number of groups (the last may
+  // be all padding).  Slice A is carried across iterations, slice B lives
+  // within one.  The prologue runs a padding emit (its stores are dropped) so
+  // that the loop is entered with the same sequence of outstanding memory
+  // operations as every later iteration: the wait for slice A then never
+  // includes the stores issued after it.
+  const int G = (((count + WAVES - 1) / WAVES) + 1) & ~1;
+  Slice sA, sB;
+  load_slice(w, sA);
+  emit(-1);
   for (int g = 0; g < G; g += 2) {
-    load_slice(WAVES * (g + 1) + w, vB);
-    if (WAVES * g + w < count) process(WAVES * g + w, vA);
+    load_slice(WAVES * (g + 1) + w, sB);
+    process(WAVES * g + w, sA);
     __syncthreads();
     emit(g);
-    __syncthreads();
-    if (g + 1 >= G) break;
-    load_slice(WAVES * (g + 2) + w, vA);
-    if (WAVES * (g + 1) + w < count) process(WAVES * (g + 1) + w, vB);
+    load_slice(WAVES * (g + 2) + w, sA);
+    process(WAVES * (g + 1) + w, sB);
     __syncthreads();
     emit(g + 1);
-    __syncthreads();
   }
 
   red_s[t] = static_cast<double>(psum);
@@ -765,15 +809,14 @@ __global__ __launch_bounds__(64 * WAVES) void stream_batch(const StepArgs* __res
 }
 
 template <typename T, int R, int TX, int TY, int NT>
-hipError_t launch_one(const StepArgs& a, hipStream_t s) {
-  const int n = a.tiles_x * a.tiles_y * a.chunks;
-  hipLaunchKernelGGL((step_single<T, R, TX, TY, NT>), dim3(n), dim3(NT), 0, s, a);
-  return hipGetLastError();
-}
-
-template <typename T, int R, int TX, int TY, int NT>
-hipError_t launch_many(const StepArgs* jobs, const int32_t* first, int njobs, int total, hipStream_t s) {
-  hipLaunchKernelGGL((step_batch<T, R, TX, TY, NT>), dim3(total), dim3(NT), 0, s, jobs, first, njobs, total);
+hipError_t launch_tiled(const StepArgs* single, const StepArgs* jobs, const int32_t* first, int njobs, int total,
+                        hipStream_t s) {
+  if (single) {
+    const int n = single->tiles_x * single->tiles_y * single->chunks;
+    hipLaunchKernelGGL((step_single<T, R, TX, TY, NT>), dim3(n), dim3(NT), 0, s, *single);
+  } else {
+    hipLaunchKernelGGL((step_batch<T, R, TX, TY, NT>), dim3(total), dim3(NT), 0, s, jobs, first, njobs, total);
+  }
   return hipGetLastError();
 }
 
@@ -790,71 +833,71 @@ hipError_t launch_stream(const StepArgs* single, const StepArgs* jobs, const int
   return hipGetLastError();
 }
 
-// Instantiated launch shapes.  Tiled kernel: (TX, TY, NT).  Streaming kernel:
-// TX = 0, TY rows per strip, NT = 64 * waves.
+// Instantiated launch shapes.  Tiled kernel: (TX, TY, NT).  Streaming
+// kernel: TX = 0, TY rows per strip, NT = 64 * waves.
 #define MCL_SHAPES(X) X(64, 16, 256) X(32, 16, 128)
-#define MCL_STREAM_SHAPES(X) X(16, 4) X(8, 4) X(12, 4)
+#define MCL_STREAM_SHAPES(X) X(16, 4) X(8, 4) X(12, 4) X(8, 8) X(4, 8) X(16, 8)
 
 template <typename T, int R>
-hipError_t dispatch_shape(int tx, int ty, int nt, const StepArgs* single, const StepArgs* jobs,
-                          const int32_t* bj, int nj, int total, hipStream_t s) {
-#define MCL_TRY_STREAM(TY_, WV_) \
-  if (tx == 0 && ty == TY_ && nt == 64 * WV_) return launch_stream<T, R, TY_, WV_>(single, jobs, bj, nj, total, s);
+hipError_t dispatch_shape(const KernelShape& k, const StepArgs* single, const StepArgs* jobs, const int32_t* bj,
+                          int nj, int total, hipStream_t s) {
+#define MCL_TRY_STREAM(TY_, WV_)                          \
+  if (k.tx == 0 && k.ty == TY_ && k.nt == 64 * WV_) \
+    return launch_stream<T, R, TY_, WV_>(single, jobs, bj, nj, total, s);
   MCL_STREAM_SHAPES(MCL_TRY_STREAM)
 #undef MCL_TRY_STREAM
-#define MCL_TRY(TX_, TY_, NT_)                                                  \
-  if (tx == TX_ && ty == TY_ && nt == NT_)                                      \
-    return single ? launch_one<T, R, TX_, TY_, NT_>(*single, s)                 \
-                  : launch_many<T, R, TX_, TY_, NT_>(jobs, bj, nj, total, s);
+#define MCL_TRY(TX_, TY_, NT_)                        \
+  if (k.tx == TX_ && k.ty == TY_ && k.nt == NT_) \
+    return launch_tiled<T, R, TX_, TY_, NT_>(single, jobs, bj, nj, total, s);
   MCL_SHAPES(MCL_TRY)
 #undef MCL_TRY
   return hipErrorInvalidValue;
 }
 
 template <typename T>
-hipError_t dispatch_radius(int radius, int tx, int ty, int nt, const StepArgs* single,
-                           const StepArgs* jobs, const int32_t* bj, int nj, int total, hipStream_t s) {
+hipError_t dispatch_radius(int radius, const KernelShape& k, const StepArgs* single, const StepArgs* jobs,
+                           const int32_t* bj, int nj, int total, hipStream_t s) {
   switch (radius) {
-    case 1: return dispatch_shape<T, 1>(tx, ty, nt, single, jobs, bj, nj, total, s);
-    case 2: return dispatch_shape<T, 2>(tx, ty, nt, single, jobs, bj, nj, total, s);
-    case 3: return dispatch_shape<T, 3>(tx, ty, nt, single, jobs, bj, nj, total, s);
-    case 4: return dispatch_shape<T, 4>(tx, ty, nt, single, jobs, bj, nj, total, s);
+    case 1: return dispatch_shape<T, 1>(k, single, jobs, bj, nj, total, s);
+    case 2: return dispatch_shape<T, 2>(k, single, jobs, bj, nj, total, s);
+    case 3: return dispatch_shape<T, 3>(k, single, jobs, bj, nj, total, s);
+    case 4: return dispatch_shape<T, 4>(k, single, jobs, bj, nj, total, s);
     default: return hipErrorInvalidValue;
   }
 }
 
-hipError_t dispatch(int dtype, int radius, int tx, int ty, int nt, const StepArgs* single,
-                    const StepArgs* jobs, const int32_t* bj, int nj, int total, hipStream_t s) {
+hipError_t dispatch(int dtype, int radius, const KernelShape& k, const StepArgs* single, const StepArgs* jobs,
+                    const int32_t* bj, int nj, int total, hipStream_t s) {
   switch (dtype) {
-    case 0: return dispatch_radius<float>(radius, tx, ty, nt, single, jobs, bj, nj, total, s);
-    case 1: return dispatch_radius<__bf16>(radius, tx, ty, nt, single, jobs, bj, nj, total, s);
-    case 2: return dispatch_radius<_Float16>(radius, tx, ty, nt, single, jobs, bj, nj, total, s);
+    case 0: return dispatch_radius<float>(radius, k, single, jobs, bj, nj, total, s);
+    case 1: return dispatch_radius<__bf16>(radius, k, single, jobs, bj, nj, total, s);
+    case 2: return dispatch_radius<_Float16>(radius, k, single, jobs, bj, nj, total, s);
     default: return hipErrorInvalidValue;
   }
 }
 
 }  // namespace
 
-bool step_config_supported(int dtype, int radius, int tx, int ty, int nt) {
+bool step_config_supported(int dtype, int radius, const KernelShape& k) {
   if (dtype < 0 || dtype > 2 || radius < 1 || radius > kMaxRadius) return false;
 #define MCL_HAS(TX_, TY_, NT_) \
-  if (tx == TX_ && ty == TY_ && nt == NT_) return true;
+  if (k.tx == TX_ && k.ty == TY_ && k.nt == NT_) return true;
   MCL_SHAPES(MCL_HAS)
 #undef MCL_HAS
 #define MCL_HAS_STREAM(TY_, WV_) \
-  if (tx == 0 && ty == TY_ && nt == 64 * WV_) return true;
+  if (k.tx == 0 && k.ty == TY_ && k.nt == 64 * WV_) return true;
   MCL_STREAM_SHAPES(MCL_HAS_STREAM)
 #undef MCL_HAS_STREAM
   return false;
 }
 
-hipError_t launch_step(int dtype, int radius, int tx, int ty, int nt, const StepArgs& a, hipStream_t s) {
-  return dispatch(dtype, radius, tx, ty, nt, &a, nullptr, nullptr, 0, 0, s);
+hipError_t launch_step(int dtype, int radius, const KernelShape& k, const StepArgs& a, hipStream_t s) {
+  return dispatch(dtype, radius, k, &a, nullptr, nullptr, 0, 0, s);
 }
 
-hipError_t launch_step_batch(int dtype, int radius, int tx, int ty, int nt, const StepArgs* jobs_dev,
+hipError_t launch_step_batch(int dtype, int radius, const KernelShape& k, const StepArgs* jobs_dev,
                              const int32_t* first_dev, int32_t njobs, int32_t total_blocks, hipStream_t s) {
-  return dispatch(dtype, radius, tx, ty, nt, nullptr, jobs_dev, first_dev, njobs, total_blocks, s);
+  return dispatch(dtype, radius, k, nullptr, jobs_dev, first_dev, njobs, total_blocks, s);
 }
 
 }  // namespace mcl

@@ -61,9 +61,12 @@ class Info(ctypes.Structure):
 
 
 class MclError(RuntimeError):
-    def __init__(self, status, message):
+    def __init__(self, status, message, readout=None):
         super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
         self.status = status
+        # read_belief on a degenerate filter still fills its outputs (the last
+        # belief that had mass): (belief, Pose, theta_offset, log_norm)
+        self.readout = readout
 
 
 _lib = None
@@ -228,8 +231,11 @@ class Filter:
         pose = Pose()
         th = c_double()
         ln = c_double()
-        _check(_lib.mcl_read_belief(self.handle, out.ctypes.data if out is not None else None, byref(pose),
-                                    byref(th), byref(ln)))
+        st = _lib.mcl_read_belief(self.handle, out.ctypes.data if out is not None else None, byref(pose),
+                                  byref(th), byref(ln))
+        if st == EDEGENERATE:
+            raise MclError(st, last_error(), readout=(out, pose, th.value, ln.value))
+        _check(st)
         return out, pose, th.value, ln.value
 
     def export_belief(self, with_map=False):

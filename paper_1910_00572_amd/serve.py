@@ -49,6 +49,7 @@ class Result:
     belief: np.ndarray | None
     pose: tuple
     log_norm: float
+    degenerate: bool = False   # a step removed all probability mass (belief kept, Sec. III-A)
 
 
 class Server:
@@ -126,10 +127,10 @@ class Server:
                 req, f = a[0], a[1]
                 states_steps += f.map.width * f.map.height * req.n_theta
                 if a[2] == len(req.odometry):
-                    b, pose, _, ln = f.read_belief(want_belief=self.keep_beliefs)
+                    b, pose, ln, degen = _final_readout(f, self.keep_beliefs)
                     results[req.rid] = Result(req.rid, a[3], time.perf_counter() - t0, a[2],
                                               f.map.width * f.map.height * req.n_theta,
-                                              b, pose.as_tuple(), ln)
+                                              b, pose, ln, degen)
                     used -= a[4]
                     del f
                     a[1] = None
@@ -152,6 +153,7 @@ class Server:
             "iterations": len(lat_events),
             "admission_wait_s_p50": float(np.percentile(waits, 50)) if waits else 0.0,
             "admission_wait_s_p99": float(np.percentile(waits, 99)) if waits else 0.0,
+            "degenerate_requests": sum(1 for r in results.values() if r.degenerate),
             "peak_bytes": peak_used,
             "peak_active": peak_active,
             "budget_bytes": self.budget,
@@ -159,13 +161,30 @@ class Server:
         return results, stats
 
 
+def _final_readout(f, want_belief):
+    """Belief, argmax pose, log-normaliser and the degenerate flag of a filter.
+
+    A filter whose mass was all removed by some step reports EDEGENERATE; its
+    readout (the last belief that had mass) is still returned.
+    """
+    try:
+        b, pose, _, ln = f.read_belief(want_belief=want_belief)
+        return b, pose.as_tuple(), ln, False
+    except mcl.MclError as e:
+        if e.status != mcl.EDEGENERATE:
+            raise
+        b, pose, _, ln = e.readout
+        return b, pose.as_tuple(), ln, True
+
+
 def run_alone(maps, req: Request, keep_belief=True):
-    """Reference: the same request on a filter of its own, one call per step."""
+    """Reference: the same request on a filter of its own, one call per step.
+
+    Returns (belief, pose, log_norm, degenerate)."""
     f = mcl.Filter(maps[req.map_key], req.n_theta, req.sigma_theta, storage=req.storage)
     for t, (u, v, w) in enumerate(req.odometry):
         f.step_odometry(u, v, w)
         z = req.scans.get(t)
         if z is not None:
             f.apply_scan(z, req.scan_sigma_m)
-    b, pose, _, ln = f.read_belief(want_belief=keep_belief)
-    return b, pose.as_tuple(), ln
+    return _final_readout(f, keep_belief)

@@ -64,6 +64,8 @@ def test_server_mix_equals_alone_and_respects_budget():
             for t in range(9, steps, 10):
                 j, i = free[rng.integers(len(free))]
                 scans[t] = noisy_scan(occ, 0.1, ((i + 0.5) * 0.1, (j + 0.5) * 0.1, 0.3), 60, 3.0, 0.1, seed=rid * 100 + t)
+        if rid == 3:
+            odo[steps // 2] = (100.0 * 0.1, 0.0, 0.0)  # a 100-cell jump: all mass leaves the grid
         reqs.append(Request(rid, float(rng.uniform(0, 0.05)), g, n_theta, storage, odo, scans, sigma_theta=0.7))
     # budget: about three of the largest filters at once
     probe = Server(mp, 1 << 40)
@@ -74,8 +76,9 @@ def test_server_mix_equals_alone_and_respects_budget():
     assert stats["peak_bytes"] <= 3 * need
     assert stats["peak_active"] >= 2  # work overlapped
     assert len(results) == len(reqs)
+    assert stats["degenerate_requests"] == 1 and results[3].degenerate
     for r in reqs:
-        b, pose, ln = run_alone(mp, r)
+        b, pose, ln, degen = run_alone(mp, r)
         got = results[r.rid]
         assert np.array_equal(got.belief, b), f"request {r.rid}"
-        assert got.pose == pose and got.log_norm == ln
+        assert got.pose == pose and got.log_norm == ln and got.degenerate == degen
