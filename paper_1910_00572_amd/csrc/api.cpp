@@ -147,13 +147,6 @@ namespace {
 
 constexpr int kReduceBlocks = 1024;
 
-// Launch shape of the step kernel.  Measured on MI355X: the tiled kernel
-// (64 x 16 tiles, 256 threads) is faster once a map has at least 512 tiles
-// (1024^2 x 128: 390 us FP32 / 367 us BF16, against 411 / 381 for the best
-// streaming shapes); on smaller maps the streaming kernel with 8-row strips
-// keeps more workgroups busy (512^2 x 72 FP32: 68 us against 87).
-// MCL_STEP_SHAPE="tx,ty,nt[,chunks]" overrides the choice (tx = 0:
-// streaming; chunks = 0: automatic).
 // The streaming kernel addresses one heading plane with 32-bit buffer offsets
 // whose out-of-grid markers start at 2^30, so a plane must stay below 1 GiB.
 bool stream_plane_ok(int W, int H, size_t eb) {
@@ -161,24 +154,42 @@ bool stream_plane_ok(int W, int H, size_t eb) {
   return pitch * static_cast<size_t>(H) * eb < (static_cast<size_t>(1) << 30);
 }
 
+// Launch shape of the step kernel, from measurements on MI355X.  Maps of
+// fewer than 512 64 x 16 tiles: streaming kernel, 8-row strips, 4 waves,
+// two slice buffers (512^2 x 72 FP32: 69 us against 87 for the tiled
+// kernel).  Larger maps: FP32 storage uses the tiled kernel (64 x 16 tiles,
+// 256 threads; 1024^2 x 128: 390 us against 413 for the best streaming
+// shape); 16-bit storage uses the streaming kernel with 16-row strips and
+// 8 waves (1024^2 x 128 BF16: 342 us against 367 tiled).
+// MCL_STEP_SHAPE="tx,ty,nt[,chunks[,nbuf]]" overrides the choice (tx = 0:
+// streaming with nbuf source-slice buffers; chunks = 0: automatic).
 StepShape choose_shape(int W, int H, int T, int R, size_t eb) {
   StepShape s;
   const int tiled_tiles = ((W + 63) / 64) * ((H + 15) / 16);
-  int sh[4] = {64, 16, 256, 0};
-  if (tiled_tiles < 512 && stream_plane_ok(W, H, eb)) {
-    sh[0] = 0;
-    sh[1] = 8;
-    sh[2] = 256;
-    sh[3] = 1;
+  int sh[5] = {64, 16, 256, 0, 2};
+  if (stream_plane_ok(W, H, eb)) {
+    if (tiled_tiles < 512) {
+      sh[0] = 0;
+      sh[1] = 8;
+      sh[2] = 256;
+      sh[3] = 1;
+    } else if (eb == 2) {
+      sh[0] = 0;
+      sh[1] = 16;
+      sh[2] = 512;
+      sh[3] = 1;
+      sh[4] = 1;
+    }
   }
   if (const char* env = getenv("MCL_STEP_SHAPE")) {
-    int v[4] = {0, 0, 0, 0};
-    if (sscanf(env, "%d,%d,%d,%d", &v[0], &v[1], &v[2], &v[3]) >= 3)
-      for (int i = 0; i < 4; ++i) sh[i] = v[i];
+    int v[5] = {0, 0, 0, 0, 2};
+    if (sscanf(env, "%d,%d,%d,%d,%d", &v[0], &v[1], &v[2], &v[3], &v[4]) >= 3)
+      for (int i = 0; i < 5; ++i) sh[i] = v[i];
   }
   s.k.tx = sh[0];
   s.k.ty = sh[1];
   s.k.nt = sh[2];
+  s.k.nbuf = sh[0] == 0 ? sh[4] : 2;
   // streaming kernel: 32-byte aligned strips unless MCL_STREAM_ALIGN says otherwise
   int align = kStreamAlignBytes;
   if (const char* env = getenv("MCL_STREAM_ALIGN")) align = atoi(env);

@@ -97,15 +97,18 @@ constexpr int stream_strip_width(int R, int elt_bytes, int align_bytes) {
 constexpr int kStreamAlignBytes = 32;
 
 // Launch shape of the step kernel.  tx > 0: tiled kernel with tx x ty tiles
-// and nt threads.  tx == 0: streaming kernel with ty-row strips and nt / 64
-// waves.
+// and nt threads.  tx == 0: streaming kernel with ty-row strips, nt / 64
+// waves and nbuf source-slice buffers.
 struct KernelShape {
-  int tx = 64, ty = 16, nt = 256;
-  bool operator==(const KernelShape& o) const { return tx == o.tx && ty == o.ty && nt == o.nt; }
+  int tx = 64, ty = 16, nt = 256, nbuf = 2;
+  bool operator==(const KernelShape& o) const {
+    return tx == o.tx && ty == o.ty && nt == o.nt && nbuf == o.nbuf;
+  }
   bool operator<(const KernelShape& o) const {
     if (tx != o.tx) return tx < o.tx;
     if (ty != o.ty) return ty < o.ty;
-    return nt < o.nt;
+    if (nt != o.nt) return nt < o.nt;
+    return nbuf < o.nbuf;
   }
 };
 hipError_t launch_step(int dtype, int radius, const KernelShape& k, const StepArgs& a, hipStream_t s);

@@ -536,25 +536,33 @@ __device__ inline float from_right(float v) {
   return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x130, 0xf, 0xf, true));
 }
 
-template <typename T, int R, int TY, int WAVES>
+template <typename T, int R, int TY, int WAVES, int NBUF>
 __device__ __forceinline__ void stream_body(const StepArgs& a, const int blk, const int nblk) {
   constexpr int NT = 64 * WAVES;
   constexpr int NS = TY + 2 * R;   // S rows
   constexpr int NR = NS + 1;       // source rows
-  // ring slots: a group's emit reads 2R + WAVES channels and the next group's
-  // process writes WAVES more, so one barrier per group suffices
-  constexpr int RS = 2 * R + 2 * WAVES;
+  constexpr int GW = WAVES;        // channels per group (one per wave)
+  // Ring slots: a group's emit reads 2R + GW channels.  With up to four waves
+  // the ring also holds the next group's GW channels, so the next process
+  // may start before every wave has finished emitting (one barrier per
+  // group); with more waves that ring would not fit three workgroups per
+  // compute unit, and a second barrier separates emit from the next process.
+  constexpr bool ONE_BARRIER = WAVES <= 4;
+  constexpr int RS = 2 * R + (ONE_BARRIER ? 2 : 1) * GW;
   constexpr int TAPS = 2 * R + 1;
   constexpr int LP = TY + 4;       // ring lane pitch (floats): conflict-free 16-byte accesses
   constexpr int EB = Elt<T>::BYTES;
   static_assert(TY % 4 == 0, "rows per strip must be a multiple of 4");
+  static_assert(NBUF == 1 || NBUF == 2, "one or two source-slice buffers");
+  static_assert(sizeof(float) * RS * 64 * LP >= NT * (sizeof(double) + sizeof(float)), "reduction fits the ring");
 
   __shared__ __attribute__((aligned(16))) float ring[RS][64][LP];
   __shared__ int pnx[kMaxTheta], pny[kMaxTheta];
   __shared__ float pfx[kMaxTheta], pfy[kMaxTheta];
-  __shared__ double red_s[NT];
-  __shared__ float red_m[NT];
   __shared__ int last_flag;
+  // the block reduction reuses the ring once every wave has left the loop
+  double* red_s = reinterpret_cast<double*>(&ring[0][0][0]);
+  float* red_m = reinterpret_cast<float*>(red_s + NT);
 
   const int t = threadIdx.x;
   const int lane = t & 63;
@@ -692,13 +700,17 @@ __device__ __forceinline__ void stream_body(const StepArgs& a, const int blk, co
   // round trip instead of one per tap.
   constexpr int RB = 4;
   auto emit = [&](int g) {
-    const int krel = WAVES * g - 2 * R + w;
+    const int krel = GW * g - 2 * R + w;
     const bool live = krel >= 0 && krel < nk;
     const int ko = kbeg + (live ? krel : 0);
     const __amdgpu_buffer_rsrc_t rs = buf_rsrc(bout + static_cast<int64_t>(ko) * sstride, live ? plane_bytes : 0u);
+    // ring slots of channels krel .. krel + 2R; krel >= -(2R + GW) (padding
+    // emits), so a multiple of RS keeps the modulus non-negative
+    constexpr int OFF = ((2 * R + GW + RS - 1) / RS) * RS;
     int slot[TAPS];
+    slot[0] = (krel + OFF) % RS;
 #pragma unroll
-    for (int l = 0; l < TAPS; ++l) slot[l] = (krel + l) % RS;
+    for (int l = 1; l < TAPS; ++l) slot[l] = slot[l - 1] + 1 == RS ? 0 : slot[l - 1] + 1;
 #pragma unroll
     for (int ob = 0; ob < TY; ob += RB) {
       float4 rv[RB / 4][TAPS];
@@ -733,26 +745,46 @@ __device__ __forceinline__ void stream_body(const StepArgs& a, const int blk, co
     }
   };
 
-  // Two-slice software pipeline over an even number of groups (the last may
-  // be all padding).  Slice A is carried across iterations, slice B lives
-  // within one.  The prologue runs a padding emit (its stores are dropped) so
-  // that the loop is entered with the same sequence of outstanding memory
-  // operations as every later iteration: the wait for slice A then never
-  // includes the stores issued after it.
-  const int G = (((count + WAVES - 1) / WAVES) + 1) & ~1;
-  Slice sA, sB;
-  load_slice(w, sA);
-  emit(-1);
-  for (int g = 0; g < G; g += 2) {
-    load_slice(WAVES * (g + 1) + w, sB);
-    process(WAVES * g + w, sA);
-    __syncthreads();
-    emit(g);
-    load_slice(WAVES * (g + 2) + w, sA);
-    process(WAVES * (g + 1) + w, sB);
-    __syncthreads();
-    emit(g + 1);
+  // Software pipeline over the groups.  The prologue runs a padding emit
+  // (its stores are dropped) so that the loop is entered with the same
+  // sequence of outstanding memory operations as every later iteration: the
+  // wait for a slice then never includes the stores issued after it.
+  // NBUF = 2: slice A is carried across iterations and slice B lives within
+  // one, so each slice's loads are issued a whole group ahead.  NBUF = 1: the
+  // next slice is loaded into the registers the current one just left, one
+  // emit ahead (fewer registers, for more waves per SIMD).
+  auto ch = [&](int g) { return GW * g + w; };
+  if constexpr (NBUF == 2) {
+    const int G = (((count + GW - 1) / GW) + 1) & ~1;  // even: the last may be padding
+    Slice sA, sB;
+    load_slice(ch(0), sA);
+    emit(-1);
+    for (int g = 0; g < G; g += 2) {
+      load_slice(ch(g + 1), sB);
+      process(ch(g), sA);
+      __syncthreads();
+      emit(g);
+      if (!ONE_BARRIER) __syncthreads();
+      load_slice(ch(g + 2), sA);
+      process(ch(g + 1), sB);
+      __syncthreads();
+      emit(g + 1);
+      if (!ONE_BARRIER) __syncthreads();
+    }
+  } else {
+    const int G = (count + GW - 1) / GW;
+    Slice sA;
+    load_slice(ch(0), sA);
+    emit(-1);
+    for (int g = 0; g < G; ++g) {
+      process(ch(g), sA);
+      load_slice(ch(g + 1), sA);
+      __syncthreads();
+      emit(g);
+      if (!ONE_BARRIER) __syncthreads();
+    }
   }
+  __syncthreads();  // the ring becomes the reduction buffer
 
   red_s[t] = static_cast<double>(psum);
   red_m[t] = pmax;
@@ -792,20 +824,29 @@ __global__ __launch_bounds__(NT) void step_batch(const StepArgs* __restrict__ jo
   step_body<T, R, TX, TY, NT>(a, g - first[j], n);
 }
 
-template <typename T, int R, int TY, int WAVES>
-__global__ __launch_bounds__(64 * WAVES) void stream_single(StepArgs a) {
-  const int n = a.tiles_x * a.tiles_y * a.chunks;
-  stream_body<T, R, TY, WAVES>(a, xcd_remap(blockIdx.x, n), n);
+// Eight-wave workgroups aim at six waves per SIMD (three workgroups per
+// compute unit), which caps the register budget.
+template <int WAVES>
+constexpr int stream_waves_per_eu() {
+  return WAVES >= 8 ? 6 : 1;
 }
 
-template <typename T, int R, int TY, int WAVES>
-__global__ __launch_bounds__(64 * WAVES) void stream_batch(const StepArgs* __restrict__ jobs,
+template <typename T, int R, int TY, int WAVES, int NBUF>
+__global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(stream_waves_per_eu<WAVES>())))
+void stream_single(StepArgs a) {
+  const int n = a.tiles_x * a.tiles_y * a.chunks;
+  stream_body<T, R, TY, WAVES, NBUF>(a, xcd_remap(blockIdx.x, n), n);
+}
+
+template <typename T, int R, int TY, int WAVES, int NBUF>
+__global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(stream_waves_per_eu<WAVES>())))
+void stream_batch(const StepArgs* __restrict__ jobs,
                                                            const int32_t* __restrict__ first, int njobs, int total) {
   const int g = xcd_remap(blockIdx.x, total);
   const int j = find_job(first, njobs, g);
   const StepArgs& a = jobs[j];
   const int n = a.tiles_x * a.tiles_y * a.chunks;
-  stream_body<T, R, TY, WAVES>(a, g - first[j], n);
+  stream_body<T, R, TY, WAVES, NBUF>(a, g - first[j], n);
 }
 
 template <typename T, int R, int TX, int TY, int NT>
@@ -820,30 +861,30 @@ hipError_t launch_tiled(const StepArgs* single, const StepArgs* jobs, const int3
   return hipGetLastError();
 }
 
-template <typename T, int R, int TY, int WAVES>
+template <typename T, int R, int TY, int WAVES, int NBUF>
 hipError_t launch_stream(const StepArgs* single, const StepArgs* jobs, const int32_t* first, int njobs, int total,
                          hipStream_t s) {
   if (single) {
     const int n = single->tiles_x * single->tiles_y * single->chunks;
-    hipLaunchKernelGGL((stream_single<T, R, TY, WAVES>), dim3(n), dim3(64 * WAVES), 0, s, *single);
+    hipLaunchKernelGGL((stream_single<T, R, TY, WAVES, NBUF>), dim3(n), dim3(64 * WAVES), 0, s, *single);
   } else {
-    hipLaunchKernelGGL((stream_batch<T, R, TY, WAVES>), dim3(total), dim3(64 * WAVES), 0, s, jobs, first, njobs,
+    hipLaunchKernelGGL((stream_batch<T, R, TY, WAVES, NBUF>), dim3(total), dim3(64 * WAVES), 0, s, jobs, first, njobs,
                        total);
   }
   return hipGetLastError();
 }
 
 // Instantiated launch shapes.  Tiled kernel: (TX, TY, NT).  Streaming
-// kernel: TX = 0, TY rows per strip, NT = 64 * waves.
+// kernel: (TY rows per strip, waves, source-slice buffers).
 #define MCL_SHAPES(X) X(64, 16, 256) X(32, 16, 128)
-#define MCL_STREAM_SHAPES(X) X(16, 4) X(8, 4) X(12, 4) X(8, 8) X(4, 8) X(16, 8)
+#define MCL_STREAM_SHAPES(X) X(8, 4, 2) X(12, 4, 2) X(16, 4, 2) X(8, 8, 1) X(16, 8, 1)
 
 template <typename T, int R>
 hipError_t dispatch_shape(const KernelShape& k, const StepArgs* single, const StepArgs* jobs, const int32_t* bj,
                           int nj, int total, hipStream_t s) {
-#define MCL_TRY_STREAM(TY_, WV_)                          \
-  if (k.tx == 0 && k.ty == TY_ && k.nt == 64 * WV_) \
-    return launch_stream<T, R, TY_, WV_>(single, jobs, bj, nj, total, s);
+#define MCL_TRY_STREAM(TY_, WV_, NB_)                                     \
+  if (k.tx == 0 && k.ty == TY_ && k.nt == 64 * WV_ && k.nbuf == NB_) \
+    return launch_stream<T, R, TY_, WV_, NB_>(single, jobs, bj, nj, total, s);
   MCL_STREAM_SHAPES(MCL_TRY_STREAM)
 #undef MCL_TRY_STREAM
 #define MCL_TRY(TX_, TY_, NT_)                        \
@@ -884,8 +925,8 @@ bool step_config_supported(int dtype, int radius, const KernelShape& k) {
   if (k.tx == TX_ && k.ty == TY_ && k.nt == NT_) return true;
   MCL_SHAPES(MCL_HAS)
 #undef MCL_HAS
-#define MCL_HAS_STREAM(TY_, WV_) \
-  if (k.tx == 0 && k.ty == TY_ && k.nt == 64 * WV_) return true;
+#define MCL_HAS_STREAM(TY_, WV_, NB_) \
+  if (k.tx == 0 && k.ty == TY_ && k.nt == 64 * WV_ && k.nbuf == NB_) return true;
   MCL_STREAM_SHAPES(MCL_HAS_STREAM)
 #undef MCL_HAS_STREAM
   return false;
