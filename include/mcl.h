@@ -116,6 +116,10 @@ size_t mcl_map_workspace_bytes(const mcl_map_desc* desc, const mcl_params* param
  * its per-cell sum of squares (dense scan update, eq. sensor update).  Uses
  * sigma_xy / radius_xy / flags of `params`; the theta fields are ignored.
  * `stream` is a hipStream_t (NULL = default stream).  Synchronous.
+ * EINVAL for a size out of [1, 65536], a non-positive cell size, n_dirs
+ * outside [1, 1024], or a quantised range table of 4 GiB or more (cells x
+ * n_dirs rounded up to 64 x 2 bytes, 4 with MCL_SCAN_F32); ENOMEM if
+ * ws_bytes is below mcl_map_workspace_bytes.
  * The map must outlive every filter created on it. */
 mcl_status mcl_map_create(const mcl_map_desc* desc, const mcl_params* params, void* dev_ws,
                           size_t ws_bytes, void* stream, mcl_map* out);

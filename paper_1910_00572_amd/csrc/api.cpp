@@ -79,7 +79,7 @@ mcl_status check_params(const mcl_params* p, bool need_theta) {
   return MCL_OK;
 }
 
-mcl_status check_desc(const mcl_map_desc* d) {
+mcl_status check_desc(const mcl_map_desc* d, const mcl_params* p) {
   if (!d) return fail(MCL_EINVAL, "desc is NULL");
   if (d->width < 1 || d->height < 1 || d->width > 65536 || d->height > 65536)
     return fail(MCL_EINVAL, "map size %dx%d out of range", d->width, d->height);
@@ -90,6 +90,13 @@ mcl_status check_desc(const mcl_map_desc* d) {
       return fail(MCL_EINVAL, "n_dirs must be in [1, %d]", kScanMaxDirs);
     if (!(d->max_range_m > 0.0) || !isfinite(d->max_range_m))
       return fail(MCL_EINVAL, "max_range_m must be > 0");
+    // the scan kernels address the quantised table with 32-bit byte offsets
+    const size_t cells = (static_cast<size_t>(d->height) * round_up(d->width, kRowAlign) + 31) / 32 * 32;
+    const size_t kpad = (static_cast<size_t>(d->n_dirs) + 63) / 64 * 64;
+    const size_t eb = (p && (p->flags & MCL_SCAN_F32)) ? 4 : 2;
+    if (cells * kpad * eb >= (static_cast<size_t>(1) << 32))
+      return fail(MCL_EINVAL, "range table of %zu bytes exceeds the 4 GiB the scan kernels address",
+                  cells * kpad * eb);
   }
   return MCL_OK;
 }
@@ -323,14 +330,14 @@ extern "C" {
 const char* mcl_last_error(void) { return g_err.c_str(); }
 
 size_t mcl_map_workspace_bytes(const mcl_map_desc* desc, const mcl_params* params) {
-  if (check_desc(desc) != MCL_OK || check_params(params, false) != MCL_OK) return 0;
+  if (check_desc(desc, params) != MCL_OK || check_params(params, false) != MCL_OK) return 0;
   return carve_map(nullptr, nullptr, desc, params);
 }
 
 mcl_status mcl_map_create(const mcl_map_desc* d, const mcl_params* p, void* ws, size_t ws_bytes,
                           void* stream, mcl_map* out) {
   if (!out) return fail(MCL_EINVAL, "out is NULL");
-  mcl_status st = check_desc(d);
+  mcl_status st = check_desc(d, p);
   if (st != MCL_OK) return st;
   if ((st = check_params(p, false)) != MCL_OK) return st;
   if (!ws) return fail(MCL_EINVAL, "workspace is NULL");

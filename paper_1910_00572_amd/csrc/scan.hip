@@ -29,9 +29,9 @@ namespace mcl {
 namespace {
 
 constexpr int kTileCells = 128;  // cells per GEMM workgroup (4 waves x 32)
-constexpr int kNChunk = 4;       // 32-wide N blocks held in accumulators at once
+constexpr int kMaxNChunk = 4;    // 32-wide channel blocks held in accumulators at once, at most
 constexpr int kScanThreads = 256;
-constexpr int kScanApplyBlocks = 1024;
+constexpr int kScanApplyBlocks = 1024;  // pass-2 workgroups at most (two partials each)
 
 typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
 typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16;
@@ -50,15 +50,45 @@ struct ScanArgs {
   int32_t sz;           // sum of squared scan counts
   float c;              // h^2 / (2 sigma^2)
   int32_t tiles;        // number of pass-1 workgroups
+  uint32_t rq_bytes;    // size of the tiled table
 };
 
+// Four consecutive stored beliefs (16-byte aligned for FP32, 8-byte for 16-bit storage).
 template <typename T>
-__device__ inline float ld_belief(const T* p) {
-  return static_cast<float>(*p);
+__device__ inline void load4(const T* p, float v[4]);
+template <>
+__device__ inline void load4<float>(const float* p, float v[4]) {
+  const float4 q = *reinterpret_cast<const float4*>(p);
+  v[0] = q.x;
+  v[1] = q.y;
+  v[2] = q.z;
+  v[3] = q.w;
 }
 template <>
-__device__ inline float ld_belief<__bf16>(const __bf16* p) {
-  return __uint_as_float(static_cast<uint32_t>(*reinterpret_cast<const uint16_t*>(p)) << 16);
+__device__ inline void load4<__bf16>(const __bf16* p, float v[4]) {
+  const uint2 q = *reinterpret_cast<const uint2*>(p);
+  v[0] = __uint_as_float(q.x << 16);
+  v[1] = __uint_as_float(q.x & 0xffff0000u);
+  v[2] = __uint_as_float(q.y << 16);
+  v[3] = __uint_as_float(q.y & 0xffff0000u);
+}
+template <>
+__device__ inline void load4<_Float16>(const _Float16* p, float v[4]) {
+  typedef __attribute__((__vector_size__(4 * sizeof(_Float16)))) _Float16 h4;
+  const h4 q = *reinterpret_cast<const h4*>(p);
+  for (int i = 0; i < 4; ++i) v[i] = static_cast<float>(q[i]);
+}
+// Store four values rounded to the storage type (round to nearest even);
+// returns the stored values as FP32 in v.
+template <typename T>
+__device__ inline void store4(T* p, float v[4]) {
+  typedef __attribute__((__vector_size__(4 * sizeof(T)))) T t4;
+  t4 q;
+  for (int i = 0; i < 4; ++i) {
+    q[i] = static_cast<T>(v[i]);
+    v[i] = static_cast<float>(q[i]);
+  }
+  *reinterpret_cast<t4*>(p) = q;
 }
 
 // ---- circulant operand ---------------------------------------------------------
@@ -87,16 +117,22 @@ __global__ void build_ct_kernel(CtArgs a) {
 
 // ---- pass 1: cross term on MFMA + likelihood epilogue ----------------------------------
 // One wave: 32 cells x (up to kNChunk*32) channels.  OP = __bf16 or float.
+//
+// The range table is stored in the order the matrix-core A operand is read
+// ("MFMA-tiled"): for every group of 32 cells and every depth step of KSTEP,
+// the 64 lanes' 16-byte operands lie contiguously (lane l = cell l % 32,
+// depth half l / 32).  One A load per step is then a single coalesced 1 KB
+// read, and the whole table is read once per scan.
 template <typename OP>
 struct Mfma;
 
 template <>
 struct Mfma<__bf16> {
   static constexpr int KSTEP = 16;  // depth per instruction
-  __device__ static inline void step(const __bf16* arow, const __bf16* brow, int k0, int half, f32x16& acc) {
-    const bf16x8 a = *reinterpret_cast<const bf16x8*>(arow + k0 + 8 * half);
-    const bf16x8 b = *reinterpret_cast<const bf16x8*>(brow + k0 + 8 * half);
-    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+  static constexpr int HALF = 8;    // depth per lane
+  using Vec = bf16x8;
+  __device__ static inline void mma(const Vec& av, const Vec& bv, f32x16& acc) {
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc, 0, 0, 0);
   }
 };
 
@@ -106,102 +142,218 @@ struct Mfma<float> {
   // chunk is permuted identically for both operands (lane half h supplies
   // depth k0 + 4h + s at sub-step s); the sum is exact, so order is free.
   static constexpr int KSTEP = 8;
-  __device__ static inline void step(const float* arow, const float* brow, int k0, int half, f32x16& acc) {
-    const float4 a = *reinterpret_cast<const float4*>(arow + k0 + 4 * half);
-    const float4 b = *reinterpret_cast<const float4*>(brow + k0 + 4 * half);
-    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a.x, b.x, acc, 0, 0, 0);
-    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a.y, b.y, acc, 0, 0, 0);
-    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a.z, b.z, acc, 0, 0, 0);
-    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a.w, b.w, acc, 0, 0, 0);
+  static constexpr int HALF = 4;
+  using Vec = float4;
+  __device__ static inline void mma(const Vec& av, const Vec& bv, f32x16& acc) {
+    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av.x, bv.x, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av.y, bv.y, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av.z, bv.z, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av.w, bv.w, acc, 0, 0, 0);
   }
 };
 
+// Element offset of table entry (cell, beta) in the MFMA-tiled layout:
+// [depth step][32-cell group][lane][HALF].  Step-major order makes the waves
+// that run at the same time (same step, neighbouring groups) read one
+// contiguous stretch of memory, spread over all HBM channels.
+template <typename OP>
+__host__ __device__ inline int64_t tiled_offset(int64_t cell, int beta, int64_t ngroups) {
+  constexpr int KSTEP = Mfma<OP>::KSTEP, HALF = Mfma<OP>::HALF;
+  const int64_t group = cell >> 5;
+  const int r = static_cast<int>(cell & 31);
+  const int step = beta / KSTEP, k = beta % KSTEP;
+  const int lane = r + 32 * (k / HALF);
+  return ((step * ngroups + group) * 64 + lane) * HALF + (k % HALF);
+}
+
 // Accumulator layout of a 32x32 MFMA: lane l holds column (l % 32); register
-// 4g + i holds row 8g + 4(l / 32) + i.  Rows are cells, columns channels.
-// With at most kNChunk*32 channels the accumulators stay in registers between
+// 4g + i holds row 8g + 4(l / 32) + i.  Rows are cells, columns channels, so
+// a lane owns runs of four consecutive cells of one channel: the epilogue
+// reads the belief and writes L in 16-byte (FP32) pieces.  With at most
+// kNChunk*32 channels the accumulators and ln B stay in registers between
 // the search for the tile's reference state and the write of L - L_ref; more
 // channels recompute the product once.
-template <typename OP, typename T, int MODE>
+template <typename OP, typename T, int MODE, int NCH, int KPAD>
 __global__ __launch_bounds__(kScanThreads) void scan_gemm_kernel(ScanArgs a) {
+  constexpr int kNChunk = NCH;  // 32-wide channel blocks held in accumulators at once
   __shared__ float red_v[kScanThreads];
   __shared__ int red_i[kScanThreads];
   __shared__ int red_d[kScanThreads];
   __shared__ float red_lb[kScanThreads];
   __shared__ double red_m[kScanThreads];
   __shared__ int last_flag;
+  constexpr int KSTEP = Mfma<OP>::KSTEP, HALF = Mfma<OP>::HALF;
   const int t = threadIdx.x;
   const int lane = t & 63, wv = t >> 6;
   const int half = lane >> 5, col = lane & 31;
   const int cell0 = blockIdx.x * kTileCells + wv * 32;
-  const OP* rq = static_cast<const OP*>(a.rq);
   const OP* ct = static_cast<const OP*>(a.ct);
   FilterDev* dev = a.dev;
   const T* bel = static_cast<const T*>(a.buf[dev->cur]);
-  const int arow_cell = min(cell0 + col, a.cells - 1);
-  const OP* arow = rq + static_cast<int64_t>(arow_cell) * a.kpad;
+  // this wave's 32-cell group of the tiled table (padded to whole groups)
+  const int64_t ngroups = (a.cells + 31) / 32;
+  const OP* agroup = static_cast<const OP*>(a.rq) + (static_cast<int64_t>(cell0 >> 5) * 64 + lane) * HALF;
+  const int64_t astep = ngroups * 64 * HALF;  // elements between depth steps
   const int nblocks = a.npad / 32;
   const int nchunks = (nblocks + kNChunk - 1) / kNChunk;
 
   f32x16 acc[kNChunk];
+  // Depth loop.  The operands of a step are loaded four steps ahead (a ring
+  // of four register sets): the A pieces stream from HBM, the B pieces (the
+  // small circulant operand) come from the caches.  The loop is unrolled by four
+  // with compile-time buffer indices and has no branch; the scheduling
+  // barriers keep the compiler from sinking loads down to their use, which
+  // would expose the memory latency at every step.  Loads past the last step
+  // repeat the last step's address and are never used.  Channel blocks past
+  // the last one (a final partial chunk) repeat the last block's operand; the
+  // epilogue ignores them.
+  using Vec = typename Mfma<OP>::Vec;
+  constexpr int PA = 4;               // prefetch depth (steps)
+  constexpr int EB = sizeof(OP);
+  const int nsteps = a.kpad / KSTEP;  // a multiple of PA: kpad is a multiple of 64
+  // Operands come through raw buffer descriptors: the per-step offsets go
+  // into the scalar offset (A: one 1 KB piece per wave and step) or the
+  // instruction's immediate offset (B), so the depth loop needs no vector
+  // address registers.  All offsets lie inside the tables.
+  const __amdgpu_buffer_rsrc_t ra = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<void*>(a.rq), static_cast<short>(0), static_cast<int>(a.rq_bytes), 0x00020000);
+  const uint32_t va = static_cast<uint32_t>(((cell0 >> 5) * 64 + lane) * HALF * EB);
+  const uint32_t astep_bytes = static_cast<uint32_t>(astep * EB);
+  const __amdgpu_buffer_rsrc_t rb = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<OP*>(ct), static_cast<short>(0), static_cast<int>(a.npad * a.kpad * EB), 0x00020000);
+  auto load_a = [&](int step, Vec& v) {
+    const uint32_t so = static_cast<uint32_t>(min(step, nsteps - 1)) * astep_bytes;
+    v = __builtin_bit_cast(Vec, __builtin_amdgcn_raw_buffer_load_b128(ra, va, so, 0));
+  };
+  auto load_b = [&](int nc, int step, Vec (&v)[kNChunk]) {
+    const uint32_t so = static_cast<uint32_t>(min(step, nsteps - 1) * KSTEP * EB);
+#pragma unroll
+    for (int b = 0; b < kNChunk; ++b) {
+      const int nb = min(nc * kNChunk + b, nblocks - 1);
+      const uint32_t vb = static_cast<uint32_t>(((nb * 32 + col) * a.kpad + HALF * half) * EB);
+      v[b] = __builtin_bit_cast(Vec, __builtin_amdgcn_raw_buffer_load_b128(rb, vb, so, 0));
+    }
+  };
   auto compute = [&](int nc) {
-    const int nb0 = nc * kNChunk;
 #pragma unroll
     for (int b = 0; b < kNChunk; ++b)
 #pragma unroll
       for (int i = 0; i < 16; ++i) acc[b][i] = 0.f;
-    for (int k0 = 0; k0 < a.kpad; k0 += Mfma<OP>::KSTEP) {
+    Vec abuf[PA];
+    Vec bbuf[PA][kNChunk];
 #pragma unroll
-      for (int b = 0; b < kNChunk; ++b)
-        if (nb0 + b < nblocks) {
-          const OP* brow = ct + static_cast<int64_t>((nb0 + b) * 32 + col) * a.kpad;
-          Mfma<OP>::step(arow, brow, k0, half, acc[b]);
+    for (int u = 0; u < PA; ++u) {
+      load_a(u, abuf[u]);
+      load_b(nc, u, bbuf[u]);
+    }
+    if constexpr (KPAD > 0) {
+      // depth known at compile time: the whole loop is unrolled, so the
+      // compiler's wait counters track every load exactly (a loop back edge
+      // makes it wait for all outstanding loads at the top of each trip)
+      constexpr int KS = KPAD / KSTEP;
+#pragma unroll
+      for (int st = 0; st < KS; st += PA) {
+#pragma unroll
+        for (int u = 0; u < PA; ++u) {
+#pragma unroll
+          for (int b = 0; b < kNChunk; ++b) Mfma<OP>::mma(abuf[u], bbuf[u][b], acc[b]);
+          __builtin_amdgcn_sched_barrier(0);
+          if (st + u + PA < KS) {
+            load_a(st + u + PA, abuf[u]);
+            load_b(nc, st + u + PA, bbuf[u]);
+          }
+          __builtin_amdgcn_sched_barrier(0);
         }
+      }
+    } else {
+      for (int st = 0; st < nsteps; st += PA) {
+#pragma unroll
+        for (int u = 0; u < PA; ++u) {
+#pragma unroll
+          for (int b = 0; b < kNChunk; ++b) Mfma<OP>::mma(abuf[u], bbuf[u][b], acc[b]);
+          __builtin_amdgcn_sched_barrier(0);
+          load_a(st + u + PA, abuf[u]);
+          load_b(nc, st + u + PA, bbuf[u]);
+          __builtin_amdgcn_sched_barrier(0);
+        }
+      }
     }
   };
-  // visit(k, cell, d) for every valid (channel, cell) of the accumulators
-  auto epilogue = [&](int nc, auto&& visit) {
+  // visit(b, g, k, cb) for every valid run of four cells cb.. of channel k
+  auto quads = [&](int nc, auto&& visit) {
 #pragma unroll
     for (int b = 0; b < kNChunk; ++b) {
       const int k = (nc * kNChunk + b) * 32 + col;
       if (nc * kNChunk + b >= nblocks || k >= a.n_theta) continue;
 #pragma unroll
-      for (int g = 0; g < 4; ++g)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const int cell = cell0 + 8 * g + 4 * half + i;
-          if (cell < a.cells) visit(k, cell, a.sz - 2 * static_cast<int>(acc[b][4 * g + i]) + a.sr[cell]);
-        }
+      for (int g = 0; g < 4; ++g) {
+        const int cb = cell0 + 8 * g + 4 * half;  // a.cells is a multiple of 8: runs are whole
+        if (cb < a.cells) visit(b, g, k, cb);
+      }
     }
   };
+  auto dist = [&](int b, int g, int i, int sr) { return a.sz - 2 * static_cast<int>(acc[b][4 * g + i]) + sr; };
 
   if (MODE == 1) {
     const int H = a.cells / a.pitch;
     for (int nc = 0; nc < nchunks; ++nc) {
       compute(nc);
-      epilogue(nc, [&](int k, int cell, int d) {
-        const int j = cell / a.pitch, x = cell % a.pitch;
-        if (x < a.W) a.dout[(static_cast<int64_t>(k) * H + j) * a.W + x] = d;
+      quads(nc, [&](int b, int g, int k, int cb) {
+        const int4 sr4 = *reinterpret_cast<const int4*>(a.sr + cb);
+        const int srv[4] = {sr4.x, sr4.y, sr4.z, sr4.w};
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int cell = cb + i;
+          const int j = cell / a.pitch, x = cell % a.pitch;
+          if (x < a.W) a.dout[(static_cast<int64_t>(k) * H + j) * a.W + x] = dist(b, g, i, srv[i]);
+        }
       });
     }
     return;
   }
 
-  // search: largest L = ln B - c D (FP32 estimate; ties -> lowest index)
+  // search: largest L = ln B - c D (FP32 estimate; ties -> lowest index).
+  // ln B is computed once per state and kept for the write pass.
+  float lbk[kNChunk][4][4];
+  int srv[4][4];
+  auto load_b4 = [&](int b, int g, int k, int cb) {
+    load4<T>(bel + static_cast<int64_t>(k) * a.sstride + cb, lbk[b][g]);
+  };
+  auto to_log = [&](int b, int g) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) lbk[b][g][i] = lbk[b][g][i] > 0.f ? logf(lbk[b][g][i]) : -INFINITY;
+  };
   float best = -INFINITY, best_lb = 0.f;
   int best_idx = -1, best_d = 0;
   for (int nc = 0; nc < nchunks; ++nc) {
     compute(nc);
-    epilogue(nc, [&](int k, int cell, int d) {
-      const float bv = ld_belief<T>(bel + static_cast<int64_t>(k) * a.sstride + cell);
-      if (bv > 0.f) {
-        const float lb = logf(bv);
-        const float L = lb - a.c * static_cast<float>(d);
-        const int idx = k * kTileCells + (cell - static_cast<int>(blockIdx.x) * kTileCells);
-        if (L > best || (L == best && idx < best_idx)) {
-          best = L;
-          best_idx = idx;
-          best_d = d;
-          best_lb = lb;
+    if (nc == 0) {
+#pragma unroll
+      for (int g = 0; g < 4; ++g) {
+        const int cb = min(cell0 + 8 * g + 4 * half, a.cells - 4);
+        const int4 sr4 = *reinterpret_cast<const int4*>(a.sr + cb);
+        srv[g][0] = sr4.x;
+        srv[g][1] = sr4.y;
+        srv[g][2] = sr4.z;
+        srv[g][3] = sr4.w;
+      }
+    }
+    quads(nc, load_b4);
+    quads(nc, [&](int b, int g, int k, int cb) {
+      to_log(b, g);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const float lb = lbk[b][g][i];
+        if (lb > -INFINITY) {
+          const int d = dist(b, g, i, srv[g][i]);
+          const float L = lb - a.c * static_cast<float>(d);
+          const int idx = k * kTileCells + (cb + i - static_cast<int>(blockIdx.x) * kTileCells);
+          if (L > best || (L == best && idx < best_idx)) {
+            best = L;
+            best_idx = idx;
+            best_d = d;
+            best_lb = lb;
+          }
         }
       }
     });
@@ -231,15 +383,23 @@ __global__ __launch_bounds__(kScanThreads) void scan_gemm_kernel(ScanArgs a) {
     // L_ref in FP64 from the stored value and the exact integer distance
     a.partials[blockIdx.x] = has_ref ? static_cast<double>(ref_lb) - static_cast<double>(a.c) * ref_d : -INFINITY;
   }
-  // write L - L_ref for every state of the tile
+  // write L - L_ref for every state of the tile (both terms are differences
+  // of nearby quantities: no large cancellation)
   for (int nc = 0; nc < nchunks; ++nc) {
     if (nchunks > 1) compute(nc);
-    epilogue(nc, [&](int k, int cell, int d) {
-      const int64_t e = static_cast<int64_t>(k) * a.sstride + cell;
-      const float bv = ld_belief<T>(bel + e);
-      float lr = -INFINITY;
-      if (bv > 0.f && has_ref) lr = (logf(bv) - ref_lb) - a.c * static_cast<float>(d - ref_d);
-      a.lrel[e] = lr;
+    quads(nc, [&](int b, int g, int k, int cb) {
+      if (nchunks > 1) {
+        load_b4(b, g, k, cb);
+        to_log(b, g);
+      }
+      float lr[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const float lb = lbk[b][g][i];
+        lr[i] = (lb > -INFINITY && has_ref) ? (lb - ref_lb) - a.c * static_cast<float>(dist(b, g, i, srv[g][i]) - ref_d)
+                                            : -INFINITY;
+      }
+      *reinterpret_cast<float4*>(a.lrel + static_cast<int64_t>(k) * a.sstride + cb) = make_float4(lr[0], lr[1], lr[2], lr[3]);
     });
   }
 
@@ -268,6 +428,9 @@ __global__ __launch_bounds__(kScanThreads) void scan_gemm_kernel(ScanArgs a) {
 }
 
 // ---- pass 2: exponentiate, store, renormalise ------------------------------------------
+// Grid (bx, channel): block (bx, k) walks runs of four cells of plane k with
+// a stride of gridDim.x runs, so every access is a 16-byte (FP32) piece and
+// the tile of a cell is a shift, not a 64-bit division.
 template <typename T>
 __global__ __launch_bounds__(kScanThreads) void scan_apply_kernel(ScanArgs a) {
   __shared__ double rs[kScanThreads];
@@ -277,21 +440,28 @@ __global__ __launch_bounds__(kScanThreads) void scan_apply_kernel(ScanArgs a) {
   FilterDev* dev = a.dev;
   const double mstar = dev->aux[0];
   if (!(mstar > -INFINITY)) return;  // degenerate: keep the belief (uniform across the grid)
-  T* bel = static_cast<T*>(a.buf[dev->cur]);
+  const int k = blockIdx.y;
+  const int blk = k * gridDim.x + blockIdx.x;
+  const int nblk = gridDim.x * gridDim.y;
+  T* plane = static_cast<T*>(a.buf[dev->cur]) + static_cast<int64_t>(k) * a.sstride;
+  const float* lplane = a.lrel + static_cast<int64_t>(k) * a.sstride;
   double* part = a.partials + a.tiles;
-  const int64_t n = static_cast<int64_t>(a.n_theta) * a.sstride;
+  const int nquads = static_cast<int>(a.sstride / 4);
   float s = 0.f, mx = 0.f;
-  for (int64_t e = blockIdx.x * static_cast<int64_t>(kScanThreads) + t; e < n;
-       e += static_cast<int64_t>(gridDim.x) * kScanThreads) {
-    const int cell = static_cast<int>(e % a.sstride);
+  for (int q = blockIdx.x * kScanThreads + t; q < nquads; q += gridDim.x * kScanThreads) {
+    const int cell = 4 * q;
     const double mt = a.partials[cell / kTileCells];
-    float v = 0.f;
-    if (mt > -INFINITY) v = expf(a.lrel[e] + static_cast<float>(mt - mstar));
-    const T st = static_cast<T>(v);
-    bel[e] = st;
-    const float vs = static_cast<float>(st);
-    s += vs;
-    mx = fmaxf(mx, vs);
+    const float4 lr = *reinterpret_cast<const float4*>(lplane + cell);
+    const float off = static_cast<float>(mt - mstar);
+    const bool live = mt > -INFINITY;
+    float v[4] = {live ? expf(lr.x + off) : 0.f, live ? expf(lr.y + off) : 0.f, live ? expf(lr.z + off) : 0.f,
+                  live ? expf(lr.w + off) : 0.f};
+    store4<T>(plane + cell, v);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      s += v[i];
+      mx = fmaxf(mx, v[i]);
+    }
   }
   rs[t] = static_cast<double>(s);
   rm[t] = mx;
@@ -304,16 +474,16 @@ __global__ __launch_bounds__(kScanThreads) void scan_apply_kernel(ScanArgs a) {
     __syncthreads();
   }
   if (t == 0) {
-    part[2 * blockIdx.x] = rs[0];
-    part[2 * blockIdx.x + 1] = static_cast<double>(rm[0]);
+    part[2 * blk] = rs[0];
+    part[2 * blk + 1] = static_cast<double>(rm[0]);
     const uint32_t prev = __hip_atomic_fetch_add(&dev->counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    last_flag = (prev == static_cast<uint32_t>(gridDim.x - 1));
+    last_flag = (prev == static_cast<uint32_t>(nblk - 1));
   }
   __syncthreads();
   if (!last_flag) return;
   double ts = 0.0;
   float tm = 0.f;
-  for (int b = t; b < static_cast<int>(gridDim.x); b += kScanThreads) {
+  for (int b = t; b < nblk; b += kScanThreads) {
     ts += __hip_atomic_load(&part[2 * b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     tm = fmaxf(tm, static_cast<float>(__hip_atomic_load(&part[2 * b + 1], __ATOMIC_RELAXED,
                                                         __HIP_MEMORY_SCOPE_AGENT)));
@@ -347,12 +517,11 @@ __global__ __launch_bounds__(kScanThreads) void scan_apply_kernel(ScanArgs a) {
 // ---- map table: quantise ranges ---------------------------------------------------------
 template <typename OP>
 __global__ void quantize_kernel(const float* __restrict__ src, OP* __restrict__ rq, int32_t* __restrict__ sr, int W,
-                                int pitch, int j0, int rows, int n_dirs, int kpad, double h) {
+                                int pitch, int j0, int rows, int n_dirs, int kpad, double h, int64_t ngroups) {
   const int local = blockIdx.x * blockDim.x + threadIdx.x;
   if (local >= rows * pitch) return;
   const int j = j0 + local / pitch, x = local % pitch;
   const int64_t cell = static_cast<int64_t>(j) * pitch + x;
-  OP* out = rq + cell * kpad;
   int32_t ss = 0;
   for (int b = 0; b < kpad; ++b) {
     int q = 0;
@@ -362,7 +531,7 @@ __global__ void quantize_kernel(const float* __restrict__ src, OP* __restrict__ 
       f = f < 0.0 ? 0.0 : (f > 256.0 ? 256.0 : f);
       q = static_cast<int>(f) - 128;
     }
-    out[b] = static_cast<OP>(static_cast<float>(q));
+    rq[tiled_offset<OP>(cell, b, ngroups)] = static_cast<OP>(static_cast<float>(q));
     ss += q * q;
   }
   sr[cell] = ss;
@@ -390,11 +559,13 @@ ScanTable scan_table_carve(Carver& c, const mcl_map_desc* d, int pitch, bool f32
   ScanTable t;
   if (!d->range_table) return t;
   t.n_dirs = d->n_dirs;
-  t.kpad = round_up_i(d->n_dirs, 32);
+  t.kpad = round_up_i(d->n_dirs, 64);  // whole groups of four depth steps (depth loop)
   t.max_range = d->max_range_m;
   t.f32 = f32;
   const size_t cells = static_cast<size_t>(d->height) * pitch;
-  t.rq = c.take(cells * t.kpad * (f32 ? 4 : 2));
+  const size_t cells_pad = (cells + 31) / 32 * 32;  // whole 32-cell groups of the tiled layout
+  t.rq_bytes = cells_pad * t.kpad * (f32 ? 4 : 2);
+  t.rq = c.take(t.rq_bytes);
   t.sr = static_cast<int32_t*>(c.take(cells * sizeof(int32_t)));
   t.stage_elems = std::max<size_t>(static_cast<size_t>(d->width) * d->n_dirs, 1u << 22);
   t.stage = static_cast<float*>(c.take(t.stage_elems * sizeof(float)));
@@ -407,6 +578,8 @@ mcl_status scan_table_build(ScanTable& t, const mcl_map_desc* d, int pitch, hipS
   const size_t row_elems = static_cast<size_t>(W) * d->n_dirs;
   const int rows_per = static_cast<int>(std::max<size_t>(1, t.stage_elems / row_elems));
   const double h = d->max_range_m / 256.0;
+  // the padding cells of the last 32-cell group stay zero
+  if (hipMemsetAsync(t.rq, 0, t.rq_bytes, s) != hipSuccess) return MCL_EDEVICE;
   for (int j0 = 0; j0 < H; j0 += rows_per) {
     const int rows = std::min(rows_per, H - j0);
     hipError_t e = hipMemcpyAsync(t.stage, d->range_table + static_cast<size_t>(j0) * row_elems,
@@ -415,10 +588,12 @@ mcl_status scan_table_build(ScanTable& t, const mcl_map_desc* d, int pitch, hipS
     const int n = rows * pitch;
     if (t.f32)
       hipLaunchKernelGGL(quantize_kernel<float>, dim3((n + 255) / 256), dim3(256), 0, s, t.stage,
-                         static_cast<float*>(t.rq), t.sr, W, pitch, j0, rows, d->n_dirs, t.kpad, h);
+                         static_cast<float*>(t.rq), t.sr, W, pitch, j0, rows, d->n_dirs, t.kpad, h,
+                         (static_cast<int64_t>(H) * pitch + 31) / 32);
     else
       hipLaunchKernelGGL(quantize_kernel<__bf16>, dim3((n + 255) / 256), dim3(256), 0, s, t.stage,
-                         static_cast<__bf16*>(t.rq), t.sr, W, pitch, j0, rows, d->n_dirs, t.kpad, h);
+                         static_cast<__bf16*>(t.rq), t.sr, W, pitch, j0, rows, d->n_dirs, t.kpad, h,
+                         (static_cast<int64_t>(H) * pitch + 31) / 32);
     if (hipGetLastError() != hipSuccess) return MCL_EDEVICE;
     // the staging buffer is reused by the next chunk
     if (hipStreamSynchronize(s) != hipSuccess) return MCL_EDEVICE;
@@ -481,8 +656,26 @@ hipError_t scan_launch(const ScanLaunch& L, const float* ranges_m, double sigma_
   a.sz = static_cast<int32_t>(sz);
   a.c = static_cast<float>(h * h / (2.0 * sigma_m * sigma_m));
   a.tiles = (a.cells + kTileCells - 1) / kTileCells;
+  a.rq_bytes = static_cast<uint32_t>(t.rq_bytes);
   const dim3 g1(a.tiles), b1(kScanThreads);
-#define MCL_GEMM(OP, T, MODE) hipLaunchKernelGGL((scan_gemm_kernel<OP, T, MODE>), g1, b1, 0, L.stream, a)
+  // channel blocks per pass: all of them when they fit (no recomputation)
+  const int nch = std::min(kMaxNChunk, ca.npad / 32);
+  // depth 384 (321..384 directions, e.g. 360) has a fully unrolled depth loop
+#define MCL_GEMM_K(OP, T, MODE, KP)                                                                    \
+  switch (nch) {                                                                                       \
+    case 1: hipLaunchKernelGGL((scan_gemm_kernel<OP, T, MODE, 1, KP>), g1, b1, 0, L.stream, a); break;  \
+    case 2: hipLaunchKernelGGL((scan_gemm_kernel<OP, T, MODE, 2, KP>), g1, b1, 0, L.stream, a); break;  \
+    case 3: hipLaunchKernelGGL((scan_gemm_kernel<OP, T, MODE, 3, KP>), g1, b1, 0, L.stream, a); break;  \
+    default: hipLaunchKernelGGL((scan_gemm_kernel<OP, T, MODE, 4, KP>), g1, b1, 0, L.stream, a); break; \
+  }
+#define MCL_GEMM(OP, T, MODE)                                \
+  do {                                                       \
+    if (MODE == 0 && t.kpad == 384) {                        \
+      MCL_GEMM_K(OP, T, MODE, (MODE == 0 ? 384 : 0))         \
+    } else {                                                 \
+      MCL_GEMM_K(OP, T, MODE, 0)                             \
+    }                                                        \
+  } while (0)
   if (dout) {
     if (t.f32) MCL_GEMM(float, float, 1);
     else MCL_GEMM(__bf16, float, 1);
@@ -498,12 +691,14 @@ hipError_t scan_launch(const ScanLaunch& L, const float* ranges_m, double sigma_
     default: return hipErrorInvalidValue;
   }
 #undef MCL_GEMM
+#undef MCL_GEMM_K
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  const int blocks2 = kScanApplyBlocks;
+  // pass 2: at most kScanApplyBlocks workgroups (two partials each)
+  const dim3 g2(std::max(1, std::min(64, kScanApplyBlocks / L.n_theta)), L.n_theta);
   switch (L.dtype) {
-    case 0: hipLaunchKernelGGL(scan_apply_kernel<float>, dim3(blocks2), dim3(kScanThreads), 0, L.stream, a); break;
-    case 1: hipLaunchKernelGGL(scan_apply_kernel<__bf16>, dim3(blocks2), dim3(kScanThreads), 0, L.stream, a); break;
-    case 2: hipLaunchKernelGGL(scan_apply_kernel<_Float16>, dim3(blocks2), dim3(kScanThreads), 0, L.stream, a); break;
+    case 0: hipLaunchKernelGGL(scan_apply_kernel<float>, g2, dim3(kScanThreads), 0, L.stream, a); break;
+    case 1: hipLaunchKernelGGL(scan_apply_kernel<__bf16>, g2, dim3(kScanThreads), 0, L.stream, a); break;
+    case 2: hipLaunchKernelGGL(scan_apply_kernel<_Float16>, g2, dim3(kScanThreads), 0, L.stream, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -14,7 +14,8 @@ struct ScanTable {
   int kpad = 0;            // n_dirs rounded up to the GEMM depth granule
   double max_range = 0.0;
   bool f32 = false;        // operands stored as FP32 instead of BF16
-  void* rq = nullptr;      // [H*pitch][kpad] centred counts (bf16 or f32)
+  void* rq = nullptr;      // centred counts (bf16 or f32), H*pitch cells x kpad, MFMA-tiled (scan.hip)
+  size_t rq_bytes = 0;
   int32_t* sr = nullptr;   // [H*pitch] sum over directions of rq^2
   float* stage = nullptr;  // FP32 upload staging
   size_t stage_elems = 0;

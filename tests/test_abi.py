@@ -59,3 +59,18 @@ def test_argument_errors_before_any_device_work():
     assert st == mcl.ENOMEM
     assert lib.mcl_step_odometry(None, 0.0, 0.0, 0.0) == mcl.EINVAL
     assert lib.mcl_normalize(None, None) == mcl.EINVAL
+
+
+def test_range_table_beyond_32_bit_offsets_is_rejected():
+    # the scan kernels address the quantised table with 32-bit byte offsets:
+    # 65536 x 65536 cells x 64 directions x 2 bytes is far beyond 4 GiB, while
+    # a 512 x 512 map with 360 directions (the scan workload) fits
+    lib = mcl.load_library()
+    occ = (ctypes.c_uint8 * 1)()
+    rt = (ctypes.c_float * 1)()
+    prm = mcl._params(sigma_xy=1.0)
+    big = mcl.MapDesc(65536, 65536, 0.05, ctypes.cast(occ, ctypes.c_void_p), ctypes.cast(rt, ctypes.c_void_p),
+                      64, 10.0)
+    assert lib.mcl_map_workspace_bytes(ctypes.byref(big), ctypes.byref(prm)) == 0
+    ok = mcl.MapDesc(512, 512, 0.05, ctypes.cast(occ, ctypes.c_void_p), ctypes.cast(rt, ctypes.c_void_p), 360, 10.0)
+    assert lib.mcl_map_workspace_bytes(ctypes.byref(ok), ctypes.byref(prm)) > 512 * 512 * 384 * 2
