@@ -716,19 +716,20 @@ mcl_status mcl_step_batch(mcl_filter* const filters, const double* uvw, int32_t 
   struct Group {
     int dtype, radius;
     KernelShape k;
-    int job0, first0, njobs, blocks;
+    int job0, first0, njobs, blocks, max_theta;
   };
   std::vector<Group> groups;
   for (size_t i = 0; i < jobs.size(); ++i) {
     if (i == 0 || !same(jobs[i], jobs[i - 1])) {
       if (!groups.empty()) first.push_back(groups.back().blocks);
       groups.push_back(Group{jobs[i].dtype, jobs[i].radius, jobs[i].k,
-                             static_cast<int>(args.size()), static_cast<int>(first.size()), 0, 0});
+                             static_cast<int>(args.size()), static_cast<int>(first.size()), 0, 0, 0});
     }
     Group& g = groups.back();
     first.push_back(g.blocks);
     args.push_back(jobs[i].a);
     g.blocks += jobs[i].a.tiles_x * jobs[i].a.tiles_y * jobs[i].a.chunks;
+    g.max_theta = std::max(g.max_theta, static_cast<int>(jobs[i].a.n_theta));
     ++g.njobs;
   }
   first.push_back(groups.back().blocks);
@@ -740,7 +741,8 @@ mcl_status mcl_step_batch(mcl_filter* const filters, const double* uvw, int32_t 
   HIP_TRY(hipMemcpyAsync(first_dev, first.data(), first.size() * sizeof(int32_t), hipMemcpyHostToDevice, s),
           "batch offsets upload");
   for (const Group& g : groups)
-    HIP_TRY(launch_step_batch(g.dtype, g.radius, g.k, args_dev + g.job0, first_dev + g.first0, g.njobs, g.blocks, s),
+    HIP_TRY(launch_step_batch(g.dtype, g.radius, g.k, args_dev + g.job0, first_dev + g.first0, g.njobs, g.blocks,
+                              g.max_theta, s),
             "batch launch");
   return MCL_OK;
 }

@@ -112,9 +112,11 @@ struct KernelShape {
   }
 };
 hipError_t launch_step(int dtype, int radius, const KernelShape& k, const StepArgs& a, hipStream_t s);
-// jobs_dev[0..njobs) with first_dev[j] = first workgroup of job j (first_dev[njobs] = total).
+// jobs_dev[0..njobs) with first_dev[j] = first workgroup of job j (first_dev[njobs] = total);
+// max_theta = the largest heading count among the jobs.
 hipError_t launch_step_batch(int dtype, int radius, const KernelShape& k, const StepArgs* jobs_dev,
-                             const int32_t* first_dev, int32_t njobs, int32_t total_blocks, hipStream_t s);
+                             const int32_t* first_dev, int32_t njobs, int32_t total_blocks, int32_t max_theta,
+                             hipStream_t s);
 bool step_config_supported(int dtype, int radius, const KernelShape& k);
 
 hipError_t launch_map_setup(const uint8_t* occ_dev, int W, int H, int pitch, const double* gxy,

@@ -557,8 +557,14 @@ __device__ __forceinline__ void stream_body(const StepArgs& a, const int blk, co
   static_assert(sizeof(float) * RS * 64 * LP >= NT * (sizeof(double) + sizeof(float)), "reduction fits the ring");
 
   __shared__ __attribute__((aligned(16))) float ring[RS][64][LP];
-  __shared__ int pnx[kMaxTheta], pny[kMaxTheta];
-  __shared__ float pfx[kMaxTheta], pfy[kMaxTheta];
+  // per-channel shift table, sized by the launch to the job's heading count
+  // (4 x 4 bytes per channel) so that small heading counts leave LDS for
+  // more resident workgroups
+  extern __shared__ int shift_table[];
+  int* pnx = shift_table;
+  int* pny = shift_table + a.n_theta;
+  float* pfx = reinterpret_cast<float*>(shift_table + 2 * a.n_theta);
+  float* pfy = reinterpret_cast<float*>(shift_table + 3 * a.n_theta);
   __shared__ int last_flag;
   // the block reduction reuses the ring once every wave has left the loop
   double* red_s = reinterpret_cast<double*>(&ring[0][0][0]);
@@ -863,13 +869,14 @@ hipError_t launch_tiled(const StepArgs* single, const StepArgs* jobs, const int3
 
 template <typename T, int R, int TY, int WAVES, int NBUF>
 hipError_t launch_stream(const StepArgs* single, const StepArgs* jobs, const int32_t* first, int njobs, int total,
-                         hipStream_t s) {
+                         int max_theta, hipStream_t s) {
+  const size_t table = static_cast<size_t>(max_theta) * 4 * sizeof(int);
   if (single) {
     const int n = single->tiles_x * single->tiles_y * single->chunks;
-    hipLaunchKernelGGL((stream_single<T, R, TY, WAVES, NBUF>), dim3(n), dim3(64 * WAVES), 0, s, *single);
+    hipLaunchKernelGGL((stream_single<T, R, TY, WAVES, NBUF>), dim3(n), dim3(64 * WAVES), table, s, *single);
   } else {
-    hipLaunchKernelGGL((stream_batch<T, R, TY, WAVES, NBUF>), dim3(total), dim3(64 * WAVES), 0, s, jobs, first, njobs,
-                       total);
+    hipLaunchKernelGGL((stream_batch<T, R, TY, WAVES, NBUF>), dim3(total), dim3(64 * WAVES), table, s, jobs, first,
+                       njobs, total);
   }
   return hipGetLastError();
 }
@@ -881,10 +888,10 @@ hipError_t launch_stream(const StepArgs* single, const StepArgs* jobs, const int
 
 template <typename T, int R>
 hipError_t dispatch_shape(const KernelShape& k, const StepArgs* single, const StepArgs* jobs, const int32_t* bj,
-                          int nj, int total, hipStream_t s) {
+                          int nj, int total, int max_theta, hipStream_t s) {
 #define MCL_TRY_STREAM(TY_, WV_, NB_)                                     \
   if (k.tx == 0 && k.ty == TY_ && k.nt == 64 * WV_ && k.nbuf == NB_) \
-    return launch_stream<T, R, TY_, WV_, NB_>(single, jobs, bj, nj, total, s);
+    return launch_stream<T, R, TY_, WV_, NB_>(single, jobs, bj, nj, total, max_theta, s);
   MCL_STREAM_SHAPES(MCL_TRY_STREAM)
 #undef MCL_TRY_STREAM
 #define MCL_TRY(TX_, TY_, NT_)                        \
@@ -897,22 +904,22 @@ hipError_t dispatch_shape(const KernelShape& k, const StepArgs* single, const St
 
 template <typename T>
 hipError_t dispatch_radius(int radius, const KernelShape& k, const StepArgs* single, const StepArgs* jobs,
-                           const int32_t* bj, int nj, int total, hipStream_t s) {
+                           const int32_t* bj, int nj, int total, int max_theta, hipStream_t s) {
   switch (radius) {
-    case 1: return dispatch_shape<T, 1>(k, single, jobs, bj, nj, total, s);
-    case 2: return dispatch_shape<T, 2>(k, single, jobs, bj, nj, total, s);
-    case 3: return dispatch_shape<T, 3>(k, single, jobs, bj, nj, total, s);
-    case 4: return dispatch_shape<T, 4>(k, single, jobs, bj, nj, total, s);
+    case 1: return dispatch_shape<T, 1>(k, single, jobs, bj, nj, total, max_theta, s);
+    case 2: return dispatch_shape<T, 2>(k, single, jobs, bj, nj, total, max_theta, s);
+    case 3: return dispatch_shape<T, 3>(k, single, jobs, bj, nj, total, max_theta, s);
+    case 4: return dispatch_shape<T, 4>(k, single, jobs, bj, nj, total, max_theta, s);
     default: return hipErrorInvalidValue;
   }
 }
 
 hipError_t dispatch(int dtype, int radius, const KernelShape& k, const StepArgs* single, const StepArgs* jobs,
-                    const int32_t* bj, int nj, int total, hipStream_t s) {
+                    const int32_t* bj, int nj, int total, int max_theta, hipStream_t s) {
   switch (dtype) {
-    case 0: return dispatch_radius<float>(radius, k, single, jobs, bj, nj, total, s);
-    case 1: return dispatch_radius<__bf16>(radius, k, single, jobs, bj, nj, total, s);
-    case 2: return dispatch_radius<_Float16>(radius, k, single, jobs, bj, nj, total, s);
+    case 0: return dispatch_radius<float>(radius, k, single, jobs, bj, nj, total, max_theta, s);
+    case 1: return dispatch_radius<__bf16>(radius, k, single, jobs, bj, nj, total, max_theta, s);
+    case 2: return dispatch_radius<_Float16>(radius, k, single, jobs, bj, nj, total, max_theta, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -933,12 +940,13 @@ bool step_config_supported(int dtype, int radius, const KernelShape& k) {
 }
 
 hipError_t launch_step(int dtype, int radius, const KernelShape& k, const StepArgs& a, hipStream_t s) {
-  return dispatch(dtype, radius, k, &a, nullptr, nullptr, 0, 0, s);
+  return dispatch(dtype, radius, k, &a, nullptr, nullptr, 0, 0, a.n_theta, s);
 }
 
 hipError_t launch_step_batch(int dtype, int radius, const KernelShape& k, const StepArgs* jobs_dev,
-                             const int32_t* first_dev, int32_t njobs, int32_t total_blocks, hipStream_t s) {
-  return dispatch(dtype, radius, k, nullptr, jobs_dev, first_dev, njobs, total_blocks, s);
+                             const int32_t* first_dev, int32_t njobs, int32_t total_blocks, int32_t max_theta,
+                             hipStream_t s) {
+  return dispatch(dtype, radius, k, nullptr, jobs_dev, first_dev, njobs, total_blocks, max_theta, s);
 }
 
 }  // namespace mcl
