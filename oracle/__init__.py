@@ -30,6 +30,7 @@ from .filter import (
     argmax_pose,
 )
 from .scan import quantize_ranges, beam_offsets, scan_sqdist, apply_scan
+from .sample import dither_intensity, floyd_steinberg, sample_mask, apply_scan_sampled
 
 __all__ = [
     "FilterState",
@@ -53,4 +54,8 @@ __all__ = [
     "beam_offsets",
     "scan_sqdist",
     "apply_scan",
+    "dither_intensity",
+    "floyd_steinberg",
+    "sample_mask",
+    "apply_scan_sampled",
 ]
