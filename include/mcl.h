@@ -186,6 +186,43 @@ mcl_status mcl_export_belief(mcl_filter f, float* dev_out, float* dev_map_out);
 mcl_status mcl_scan_sqdist(mcl_filter f, const float* ranges_m, int32_t n_beams,
                            int32_t* dev_out);
 
+/* sample_cells (async): the Floyd-Steinberg sample set of the belief map
+ * (Sec. III-B, dithering).  m(i, j) = max_k of the stored belief (Sec. III-A,
+ * last paragraph); intensity I = min(1, n_samples * m / sum m), the sum in
+ * FP64 rounded to FP32, product and quotient in FP32; then error diffusion as
+ * mcl_dither.  About n_samples cells are selected.  dev_mask: device uint8,
+ * H*W dense (row stride W), written with 1 (selected) or 0.  Uses the
+ * filter's staging area.  EINVAL for n_samples < 0 or a map beyond the
+ * dithering kernel (see mcl_dither). */
+mcl_status mcl_sample_cells(mcl_filter f, int32_t n_samples, uint8_t* dev_mask);
+
+/* apply_scan_sampled (async): the observation update (eq. sensor update) on
+ * the sampled states only (Sec. III-B): every heading channel of each cell
+ * whose dev_mask byte (device, H*W dense) is nonzero.  With D the squared
+ * distance of mcl_scan_sqdist and D* its minimum over the sampled states, a
+ * sampled state is multiplied by exp(-c (D - D*)), c = h^2 / (2 sigma_m^2),
+ * h = max_range / 256; unsampled states keep their value (they take the
+ * likelihood of the best-matching sample).  Then the belief is renormalised
+ * and the log-normaliser grows by ln(kept mass) - c D*.  An empty mask
+ * changes nothing.  If no mass is left the belief is kept and the filter
+ * reports MCL_EDEGENERATE.  Arguments as mcl_apply_scan; ESTATE without a
+ * range table; EINVAL for a NULL mask or 2^31 states or more. */
+mcl_status mcl_apply_scan_sampled(mcl_filter f, const float* ranges_m, int32_t n_beams, double sigma_m,
+                                  const uint8_t* dev_mask);
+
+/* dither (async): Floyd-Steinberg error diffusion of a device FP32 image
+ * (H*W dense, any values) into dev_mask (device uint8, H*W): raster order,
+ * threshold 1/2 (selected if intensity plus received error >= 1/2), error
+ * weights 7/16 right, 3/16 below-left, 5/16 below, 1/16 below-right, error
+ * leaving the image dropped.  Received error is summed in raster arrival
+ * order; every product and sum is FP32 rounded to nearest, no fused
+ * multiply-add.  `stream` is a hipStream_t (NULL = default stream).  A zero
+ * width or height does nothing.  EINVAL for negative sizes, NULL pointers,
+ * W * H >= 2^29, or min(H, W / 2 + 1) above 4096 (the error ring of the
+ * wavefront kernel lives in 64 KB of LDS). */
+mcl_status mcl_dither(const float* dev_intensity, int32_t width, int32_t height, uint8_t* dev_mask,
+                      void* stream);
+
 /* Launch shape, sizes and scalars.  sync != 0 waits for the stream first so
  * log_norm and status are current. */
 mcl_status mcl_get_info(mcl_filter f, int sync, mcl_info* out);

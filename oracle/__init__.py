@@ -30,7 +30,7 @@ from .filter import (
     argmax_pose,
 )
 from .scan import quantize_ranges, beam_offsets, scan_sqdist, apply_scan
-from .sample import dither_intensity, floyd_steinberg, sample_mask, apply_scan_sampled
+from .sample import dither_intensity, floyd_steinberg, floyd_steinberg_c, sample_mask, apply_scan_sampled
 
 __all__ = [
     "FilterState",
@@ -56,6 +56,7 @@ __all__ = [
     "apply_scan",
     "dither_intensity",
     "floyd_steinberg",
+    "floyd_steinberg_c",
     "sample_mask",
     "apply_scan_sampled",
 ]

@@ -27,7 +27,10 @@ detail; the readings taken here (listed in the design doc):
 
 from __future__ import annotations
 
+import ctypes
 import math
+import os
+import subprocess
 
 import numpy as np
 
@@ -67,6 +70,41 @@ def floyd_steinberg(intensity: np.ndarray) -> np.ndarray:
                 err[j + 1, i] = _F(err[j + 1, i] + _F(_W_BELOW * e))
                 if i + 1 < W:
                     err[j + 1, i + 1] = _F(err[j + 1, i + 1] + _F(_W_BELOW_RIGHT * e))
+    return out
+
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_FS_SRC = os.path.join(_HERE, "fs_dither.c")
+_FS_LIB = os.path.join(_HERE, "_fs_dither.so")
+_fs = None
+
+
+def build_c(force: bool = True) -> str:
+    """Compile fs_dither.c (gcc, no contraction of products into sums)."""
+    if force or not os.path.exists(_FS_LIB):
+        tmp = _FS_LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-shared", "-fPIC",
+                               _FS_SRC, "-o", tmp])
+        os.replace(tmp, _FS_LIB)
+    return _FS_LIB
+
+
+def floyd_steinberg_c(intensity: np.ndarray) -> np.ndarray:
+    """`floyd_steinberg` in C (same operations in the same order), for large images."""
+    global _fs
+    if _fs is None:
+        if not os.path.exists(_FS_LIB):
+            build_c(force=False)
+        lib = ctypes.CDLL(_FS_LIB)
+        lib.oracle_fs_dither.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_void_p]
+        lib.oracle_fs_dither.restype = ctypes.c_int
+        _fs = lib
+    img = np.ascontiguousarray(intensity, dtype=np.float32)
+    H, W = img.shape
+    out = np.zeros((H, W), np.uint8)
+    if H and W:
+        if _fs.oracle_fs_dither(img.ctypes.data, W, H, out.ctypes.data) != 0:
+            raise MemoryError("fs_dither: out of memory")
     return out
 
 

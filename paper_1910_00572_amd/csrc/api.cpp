@@ -140,6 +140,7 @@ struct mcl_filter_s {
   int n_partials = 0;
   FilterDev* dev = nullptr;
   float* scan_scratch = nullptr;
+  int32_t* samp_list = nullptr;  // sampled update: selected cells, then positions (2 x H * pitch)
   ScanWork scanw;
   int64_t sstride = 0;
   double theta = 0.0;
@@ -283,7 +284,11 @@ size_t carve_filter(mcl_filter f, void* ws, const mcl_map m, const mcl_params* p
   double* partials = static_cast<double*>(c.take(static_cast<size_t>(np) * 3 * sizeof(double)));
   FilterDev* dev = static_cast<FilterDev*>(c.take(sizeof(FilterDev)));
   float* scratch = nullptr;
-  if (m->scan.n_dirs > 0) scratch = static_cast<float*>(c.take(n * sizeof(float)));
+  int32_t* samp = nullptr;
+  if (m->scan.n_dirs > 0) {
+    scratch = static_cast<float*>(c.take(n * sizeof(float)));
+    samp = static_cast<int32_t*>(c.take(2 * static_cast<size_t>(sstride) * sizeof(int32_t)));
+  }
   void* scanw = c.take(scan_work_bytes(p->n_theta, m->scan.kpad));
   if (f) {
     f->buf[0] = b0;
@@ -293,6 +298,7 @@ size_t carve_filter(mcl_filter f, void* ws, const mcl_map m, const mcl_params* p
     f->n_partials = np;
     f->dev = dev;
     f->scan_scratch = scratch;
+    f->samp_list = samp;
     f->scanw = scan_work_carve(scanw, p->n_theta, m->scan.kpad);
     f->sstride = sstride;
     f->shape = sh;
@@ -596,16 +602,20 @@ mcl_status mcl_get_info(mcl_filter f, int sync, mcl_info* out) {
   return MCL_OK;
 }
 
-static mcl_status scan_common(mcl_filter f, const float* ranges_m, int32_t n_beams, double sigma_m,
-                              int32_t* dout) {
+static mcl_status scan_check(mcl_filter f, const float* ranges_m, int32_t n_beams, double sigma_m, bool need_sigma) {
   if (!f) return fail(MCL_EINVAL, "filter is NULL");
   const ScanTable& t = f->map->scan;
   if (t.n_dirs == 0) return fail(MCL_ESTATE, "the map has no range table");
   if (!ranges_m) return fail(MCL_EINVAL, "ranges is NULL");
   if (n_beams != t.n_dirs) return fail(MCL_EINVAL, "n_beams %d differs from the table's %d directions", n_beams, t.n_dirs);
-  if (!dout && (!(sigma_m > 0.0) || !isfinite(sigma_m))) return fail(MCL_EINVAL, "sigma_m must be > 0");
+  if (need_sigma && (!(sigma_m > 0.0) || !isfinite(sigma_m))) return fail(MCL_EINVAL, "sigma_m must be > 0");
   for (int b = 0; b < n_beams; ++b)
     if (!isfinite(ranges_m[b])) return fail(MCL_EINVAL, "range %d is not finite", b);
+  return MCL_OK;
+}
+
+static ScanLaunch scan_args(mcl_filter f) {
+  const ScanTable& t = f->map->scan;
   ScanLaunch L;
   L.table = &t;
   L.work = f->scanw;
@@ -622,7 +632,14 @@ static mcl_status scan_common(mcl_filter f, const float* ranges_m, int32_t n_bea
   L.sstride = f->sstride;
   L.theta = f->theta;
   L.stream = f->stream;
-  HIP_TRY(scan_launch(L, ranges_m, sigma_m, dout), "scan launch");
+  return L;
+}
+
+static mcl_status scan_common(mcl_filter f, const float* ranges_m, int32_t n_beams, double sigma_m,
+                              int32_t* dout) {
+  const mcl_status st = scan_check(f, ranges_m, n_beams, sigma_m, dout == nullptr);
+  if (st != MCL_OK) return st;
+  HIP_TRY(scan_launch(scan_args(f), ranges_m, sigma_m, dout), "scan launch");
   return MCL_OK;
 }
 
@@ -633,6 +650,47 @@ mcl_status mcl_apply_scan(mcl_filter f, const float* ranges_m, int32_t n_beams, 
 mcl_status mcl_scan_sqdist(mcl_filter f, const float* ranges_m, int32_t n_beams, int32_t* dev_out) {
   if (!dev_out) return fail(MCL_EINVAL, "dev_out is NULL");
   return scan_common(f, ranges_m, n_beams, 1.0, dev_out);
+}
+
+mcl_status mcl_apply_scan_sampled(mcl_filter f, const float* ranges_m, int32_t n_beams, double sigma_m,
+                                  const uint8_t* dev_mask) {
+  const mcl_status st = scan_check(f, ranges_m, n_beams, sigma_m, true);
+  if (st != MCL_OK) return st;
+  if (!dev_mask) return fail(MCL_EINVAL, "dev_mask is NULL");
+  const int64_t cells = static_cast<int64_t>(f->map->H) * f->map->pitch;
+  if (cells >= (static_cast<int64_t>(1) << 31) || cells * f->T >= (static_cast<int64_t>(1) << 31))
+    return fail(MCL_EINVAL, "the sampled update supports fewer than 2^31 states");
+  HIP_TRY(scan_sampled_launch(scan_args(f), ranges_m, sigma_m, dev_mask, f->samp_list, f->samp_list + cells),
+          "sampled scan launch");
+  return MCL_OK;
+}
+
+mcl_status mcl_sample_cells(mcl_filter f, int32_t n_samples, uint8_t* dev_mask) {
+  if (!f) return fail(MCL_EINVAL, "filter is NULL");
+  if (!dev_mask) return fail(MCL_EINVAL, "dev_mask is NULL");
+  if (n_samples < 0) return fail(MCL_EINVAL, "n_samples must be >= 0");
+  const mcl_map m = f->map;
+  if (!dither_supported(m->W, m->H))
+    return fail(MCL_EINVAL, "a %d x %d map is beyond the dithering kernel (min(H, W/2 + 1) too large)", m->W, m->H);
+  HIP_TRY(launch_dither_source(f->dtype, f->buf[0], f->buf[1], m->W, m->H, m->pitch, f->T, f->sstride, f->partials,
+                               f->dev, f->staging, f->stream),
+          "belief map");
+  HIP_TRY(launch_dither(f->staging, m->W, m->H, dev_mask, true, static_cast<float>(n_samples), f->dev, f->stream),
+          "dithering");
+  return MCL_OK;
+}
+
+mcl_status mcl_dither(const float* dev_intensity, int32_t width, int32_t height, uint8_t* dev_mask, void* stream) {
+  if (width < 0 || height < 0) return fail(MCL_EINVAL, "negative size %d x %d", width, height);
+  if (width == 0 || height == 0) return MCL_OK;
+  if (!dev_intensity || !dev_mask) return fail(MCL_EINVAL, "NULL image or mask");
+  if (!dither_supported(width, height))
+    return fail(MCL_EINVAL, "a %d x %d image is beyond the dithering kernel (min(H, W/2 + 1) too large)", width,
+                height);
+  HIP_TRY(launch_dither(dev_intensity, width, height, dev_mask, false, 1.f, nullptr,
+                        static_cast<hipStream_t>(stream)),
+          "dithering");
+  return MCL_OK;
 }
 
 static size_t batch_bytes(int32_t n) {

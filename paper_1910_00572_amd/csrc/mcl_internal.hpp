@@ -30,6 +30,11 @@ struct FilterDev {
   int64_t argmax_idx;  // flat (k, j, i) index of the readout argmax
   float argmax_val;
   float pad1;
+  // sampled observation update
+  int32_t nsel;        // cells in the sample list (appended by the compaction, cleared by the update)
+  int32_t dstar;       // smallest squared distance over the sampled states (INT32_MAX: no sample)
+  float dither_total;  // FP32 sum of the belief map the dithering scales by
+  int32_t pad2;
 };
 
 // Everything one step of one filter needs.  Passed by value for a single
@@ -131,5 +136,18 @@ hipError_t launch_export(int dtype, const void* buf, int W, int H, int pitch, in
                          int64_t sstride, const FilterDev* dev, float* out, int64_t out_slice_stride,
                          int k_begin, int k_end, float* map_out, hipStream_t s);
 hipError_t launch_dev_init(FilterDev* dev, double sum, float maxval, hipStream_t s);
+
+// Floyd-Steinberg sample selection (sample.hip).  src: H x W dense FP32,
+// either the intensity itself (scaled == false) or the belief map, turned into
+// min(1, n_samples * m / total) with the total from dev->dither_total.
+// dither_supported() says whether a W x H image fits the kernel's LDS ring.
+bool dither_supported(int W, int H);
+hipError_t launch_dither(const float* src, int W, int H, uint8_t* mask, bool scaled, float n_samples,
+                         const FilterDev* dev, hipStream_t s);
+// Belief map max_k B of the stored belief into out (H x W dense FP32) and the
+// FP32-rounded FP64 sum of it into dev->dither_total.
+hipError_t launch_dither_source(int dtype, const void* buf0, const void* buf1, int W, int H, int pitch,
+                                int n_theta, int64_t sstride, double* partials, FilterDev* dev, float* out,
+                                hipStream_t s);
 
 }  // namespace mcl

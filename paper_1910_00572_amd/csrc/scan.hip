@@ -514,6 +514,269 @@ __global__ __launch_bounds__(kScanThreads) void scan_apply_kernel(ScanArgs a) {
   }
 }
 
+// ---- sampled observation update ---------------------------------------------------------
+// The update of eq. (sensor update) on the states of the cells a selection
+// mask holds (the Floyd-Steinberg samples of the belief map, Sec. III-B).  A
+// state that is not sampled takes the likelihood of the best-matching sample,
+// so unsampled states keep their stored value and a sampled state is
+// multiplied by exp(-c (D - D*)), D* the smallest distance over the samples.
+//
+//   compact  mask -> list of the selected cells (any order) and, for every
+//            cell of the pitch layout, its position in the list (-1: not
+//            selected)
+//   pass 1   D of every sampled state on the matrix cores: the dense product
+//            restricted to the listed rows of the range table (each lane
+//            gathers its own 16-byte operand pieces); D* by a last-workgroup
+//            reduction.  D is stored per (list position, channel).
+//   pass 2   the whole belief is read once for its sum and max; sampled
+//            states are multiplied in place and their old values kept where
+//            D was.  The last workgroup updates the log-normaliser by
+//            ln sum - c D* - ln(previous sum), or, if no mass is left, puts
+//            the old values back and flags the filter degenerate.
+struct SampledArgs {
+  const void* rq;       // MFMA-tiled range table
+  const int32_t* sr;    // [cells] sum of squares per cell
+  const void* ct;       // [npad][kpad] circulant operand
+  void* buf[2];
+  const uint8_t* mask;  // H x W dense selection
+  int32_t* list;        // [nsel] selected cells (pitch layout)
+  int32_t* pos;         // [cells] position in the list, -1 = not selected
+  int32_t* dsc;         // [nsel][n_theta] D (pass 1), then the old value as FP32 bits (pass 2)
+  double* partials;     // pass 1: one per workgroup; pass 2: two per workgroup after them
+  FilterDev* dev;
+  int32_t cells, n_theta, npad, kpad, W, H, pitch;
+  int64_t sstride;
+  int32_t sz;           // sum of squared scan counts
+  float c;              // h^2 / (2 sigma^2), FP32 (factors)
+  double c64;           // the same in FP64 (log-normaliser)
+  int32_t p1_blocks;    // pass-1 workgroups (offset of the pass-2 partials)
+  int32_t kchunk;       // channels per pass-2 workgroup
+  uint32_t rq_bytes;
+};
+
+constexpr int kCompactThreads = 256;
+
+__global__ __launch_bounds__(kCompactThreads) void compact_kernel(SampledArgs a) {
+  const int lane = threadIdx.x & 63;
+  const uint32_t n = static_cast<uint32_t>(a.cells);
+  for (uint32_t c0 = blockIdx.x * kCompactThreads; c0 < n; c0 += gridDim.x * kCompactThreads) {
+    const uint32_t cell = c0 + threadIdx.x;
+    const uint32_t j = cell / static_cast<uint32_t>(a.pitch), i = cell - j * static_cast<uint32_t>(a.pitch);
+    const bool sel = cell < n && i < static_cast<uint32_t>(a.W) && a.mask[j * static_cast<uint32_t>(a.W) + i] != 0;
+    const uint64_t bal = __ballot(sel);
+    const int cnt = __popcll(bal);
+    int base = 0;
+    if (cnt > 0 && lane == 0)
+      base = __hip_atomic_fetch_add(&a.dev->nsel, cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    base = __shfl(base, 0);
+    const int idx = base + __popcll(bal & ((1ull << lane) - 1ull));
+    if (sel) a.list[idx] = static_cast<int32_t>(cell);
+    if (cell < n) a.pos[cell] = sel ? idx : -1;
+  }
+}
+
+// Pass 1.  One work item = 32 listed cells x one 32-channel block.
+template <typename OP>
+__global__ __launch_bounds__(kScanThreads) void sampled_gemm_kernel(SampledArgs a) {
+  __shared__ int red[kScanThreads / 64];
+  __shared__ double red_d[kScanThreads];
+  __shared__ int last_flag;
+  constexpr int KSTEP = Mfma<OP>::KSTEP, HALF = Mfma<OP>::HALF, EB = sizeof(OP);
+  using Vec = typename Mfma<OP>::Vec;
+  constexpr int PA = 4;
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  const int half = lane >> 5, col = lane & 31;
+  FilterDev* dev = a.dev;
+  const int nsel = __hip_atomic_load(&dev->nsel, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  const int nblocks = a.npad / 32;
+  const int items = (nsel + 31) / 32 * nblocks;
+  const int64_t ngroups = (a.cells + 31) / 32;
+  const uint32_t astep_bytes = static_cast<uint32_t>(ngroups * 64 * HALF * EB);
+  const int nsteps = a.kpad / KSTEP;  // a multiple of PA
+  const __amdgpu_buffer_rsrc_t ra = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<void*>(a.rq), static_cast<short>(0), static_cast<int>(a.rq_bytes), 0x00020000);
+  const __amdgpu_buffer_rsrc_t rb = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<void*>(a.ct), static_cast<short>(0), static_cast<int>(a.npad * a.kpad * EB), 0x00020000);
+  int dmin = INT32_MAX;
+  for (int it = blockIdx.x * (kScanThreads / 64) + wv; it < items; it += gridDim.x * (kScanThreads / 64)) {
+    const int grp = it / nblocks, nb = it - grp * nblocks;
+    const int cell = a.list[min(grp * 32 + col, nsel - 1)];
+    const uint32_t va = static_cast<uint32_t>(((cell >> 5) * 64 + (cell & 31) + 32 * half) * HALF * EB);
+    const uint32_t vb = static_cast<uint32_t>(((nb * 32 + col) * a.kpad + HALF * half) * EB);
+    auto load = [&](int st, Vec& av, Vec& bv) {
+      const int sc = min(st, nsteps - 1);
+      av = __builtin_bit_cast(Vec, __builtin_amdgcn_raw_buffer_load_b128(ra, va, static_cast<uint32_t>(sc) * astep_bytes, 0));
+      bv = __builtin_bit_cast(Vec, __builtin_amdgcn_raw_buffer_load_b128(rb, vb, static_cast<uint32_t>(sc * KSTEP * EB), 0));
+    };
+    f32x16 acc;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) acc[i] = 0.f;
+    Vec abuf[PA], bbuf[PA];
+#pragma unroll
+    for (int u = 0; u < PA; ++u) load(u, abuf[u], bbuf[u]);
+    for (int st = 0; st < nsteps; st += PA) {
+#pragma unroll
+      for (int u = 0; u < PA; ++u) {
+        Mfma<OP>::mma(abuf[u], bbuf[u], acc);
+        __builtin_amdgcn_sched_barrier(0);
+        load(st + u + PA, abuf[u], bbuf[u]);
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    }
+    // rows are list positions, columns channels (accumulator layout of the dense pass)
+    const int srv = a.sr[cell];
+    const int k = nb * 32 + col;
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int rho = 8 * g + 4 * half + i;
+        const int sr_r = __shfl(srv, rho);
+        const int r = grp * 32 + rho;
+        if (r < nsel && k < a.n_theta) {
+          const int d = a.sz - 2 * static_cast<int>(acc[4 * g + i]) + sr_r;
+          a.dsc[static_cast<int64_t>(r) * a.n_theta + k] = d;
+          dmin = min(dmin, d);
+        }
+      }
+    }
+  }
+  // D* over the grid
+  for (int o = 32; o > 0; o >>= 1) dmin = min(dmin, __shfl_xor(dmin, o));
+  if (lane == 0) red[wv] = dmin;
+  __syncthreads();
+  if (t == 0) {
+    int m = red[0];
+    for (int w = 1; w < kScanThreads / 64; ++w) m = min(m, red[w]);
+    a.partials[blockIdx.x] = static_cast<double>(m);
+    const uint32_t prev = __hip_atomic_fetch_add(&dev->counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    last_flag = (prev == gridDim.x - 1);
+  }
+  __syncthreads();
+  if (!last_flag) return;
+  double m = static_cast<double>(INT32_MAX);
+  for (int b = t; b < static_cast<int>(gridDim.x); b += kScanThreads)
+    m = fmin(m, __hip_atomic_load(&a.partials[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+  red_d[t] = m;
+  __syncthreads();
+  for (int st = kScanThreads / 2; st > 0; st >>= 1) {
+    if (t < st) red_d[t] = fmin(red_d[t], red_d[t + st]);
+    __syncthreads();
+  }
+  if (t == 0) {
+    dev->dstar = static_cast<int32_t>(red_d[0]);
+    __hip_atomic_store(&dev->counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+// Pass 2.  Grid (quad blocks, channel chunks): a thread takes runs of four
+// cells and walks the chunk's channels, so the positions are read once per
+// chunk.
+template <typename T>
+__global__ __launch_bounds__(kScanThreads) void sampled_apply_kernel(SampledArgs a) {
+  __shared__ double rs[kScanThreads];
+  __shared__ float rm[kScanThreads];
+  __shared__ int last_flag;
+  const int t = threadIdx.x;
+  FilterDev* dev = a.dev;
+  const int dstar = dev->dstar;
+  if (dstar == INT32_MAX) return;  // no sample: no update (uniform across the grid)
+  T* bel = static_cast<T*>(a.buf[dev->cur]);
+  float* old = reinterpret_cast<float*>(a.dsc);
+  const int k0 = blockIdx.y * a.kchunk, k1 = min(a.n_theta, k0 + a.kchunk);
+  const int blk = blockIdx.y * gridDim.x + blockIdx.x;
+  const int nblk = gridDim.x * gridDim.y;
+  double* part = a.partials + a.p1_blocks;
+  const int nquads = a.cells / 4;
+  double s = 0.0;
+  float mx = 0.f;
+  for (int q = blockIdx.x * kScanThreads + t; q < nquads; q += gridDim.x * kScanThreads) {
+    const int cell = 4 * q;
+    const int4 p4 = *reinterpret_cast<const int4*>(a.pos + cell);
+    const int pr[4] = {p4.x, p4.y, p4.z, p4.w};
+    const bool any = (p4.x & p4.y & p4.z & p4.w) >= 0;  // some position is not -1
+    for (int k = k0; k < k1; ++k) {
+      T* p = bel + static_cast<int64_t>(k) * a.sstride + cell;
+      float v[4];
+      load4<T>(p, v);
+      if (any) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          if (pr[u] >= 0) {
+            const int64_t idx = static_cast<int64_t>(pr[u]) * a.n_theta + k;
+            const int d = a.dsc[idx];
+            old[idx] = v[u];
+            v[u] = v[u] * expf(-a.c * static_cast<float>(d - dstar));
+          }
+        }
+        store4<T>(p, v);
+      }
+      s += static_cast<double>((v[0] + v[1]) + (v[2] + v[3]));
+      mx = fmaxf(mx, fmaxf(fmaxf(v[0], v[1]), fmaxf(v[2], v[3])));
+    }
+  }
+  rs[t] = s;
+  rm[t] = mx;
+  __syncthreads();
+  for (int st = kScanThreads / 2; st > 0; st >>= 1) {
+    if (t < st) {
+      rs[t] += rs[t + st];
+      rm[t] = fmaxf(rm[t], rm[t + st]);
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    part[2 * blk] = rs[0];
+    part[2 * blk + 1] = static_cast<double>(rm[0]);
+    const uint32_t prev = __hip_atomic_fetch_add(&dev->counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    last_flag = (prev == static_cast<uint32_t>(nblk - 1));
+  }
+  __syncthreads();
+  if (!last_flag) return;
+  double ts = 0.0;
+  float tm = 0.f;
+  for (int b = t; b < nblk; b += kScanThreads) {
+    ts += __hip_atomic_load(&part[2 * b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    tm = fmaxf(tm, static_cast<float>(__hip_atomic_load(&part[2 * b + 1], __ATOMIC_RELAXED,
+                                                        __HIP_MEMORY_SCOPE_AGENT)));
+  }
+  rs[t] = ts;
+  rm[t] = tm;
+  __syncthreads();
+  for (int st = kScanThreads / 2; st > 0; st >>= 1) {
+    if (t < st) {
+      rs[t] += rs[t + st];
+      rm[t] = fmaxf(rm[t], rm[t + st]);
+    }
+    __syncthreads();
+  }
+  const double tot = rs[0];
+  const float m = rm[0];
+  const bool degenerate = !(tot > 0.0) || !isfinite(tot) || !(m > 0.f);
+  const int nsel = __hip_atomic_load(&dev->nsel, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (degenerate) {
+    // every sampled state went to zero and nothing else holds mass: restore
+    const int64_t n = static_cast<int64_t>(nsel) * a.n_theta;
+    for (int64_t e = t; e < n; e += kScanThreads) {
+      const int r = static_cast<int>(e / a.n_theta), k = static_cast<int>(e - static_cast<int64_t>(r) * a.n_theta);
+      bel[static_cast<int64_t>(k) * a.sstride + a.list[r]] = static_cast<T>(old[e]);
+    }
+  }
+  if (t == 0) {
+    if (degenerate) {
+      dev->status = kStatusDegenerate;
+    } else {
+      dev->log_norm += log(tot) - a.c64 * static_cast<double>(dstar) - dev->lnsum;
+      dev->lnsum = log(tot);
+      dev->sum = tot;
+      dev->maxval = m;
+      dev->scale = 1.0f / m;
+    }
+    dev->nsel = 0;
+    __hip_atomic_store(&dev->counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
 // ---- map table: quantise ranges ---------------------------------------------------------
 template <typename OP>
 __global__ void quantize_kernel(const float* __restrict__ src, OP* __restrict__ rq, int32_t* __restrict__ sr, int W,
@@ -605,11 +868,14 @@ mcl_status scan_table_build(ScanTable& t, const mcl_map_desc* d, int pitch, hipS
 
 namespace mcl {
 
-hipError_t scan_launch(const ScanLaunch& L, const float* ranges_m, double sigma_m, int32_t* dout) {
+namespace {
+
+// Quantise the scan, compute the beam offsets s_k of every channel and build
+// the circulant operand C; returns the sum of squared scan counts in *sz.
+hipError_t build_ct(const ScanLaunch& L, const float* ranges_m, CtArgs& ca, int64_t* sz_out) {
   const ScanTable& t = *L.table;
   const int N = t.n_dirs;
   const double h = t.max_range / 256.0;
-  CtArgs ca;
   ca.ct = L.work.c;
   ca.n_dirs = N;
   ca.n_theta = L.n_theta;
@@ -633,7 +899,18 @@ hipError_t scan_launch(const ScanLaunch& L, const float* ranges_m, double sigma_
   }
   const int nct = ca.npad * ca.kpad;
   hipLaunchKernelGGL(build_ct_kernel, dim3((nct + 255) / 256), dim3(256), 0, L.stream, ca);
-  hipError_t e = hipGetLastError();
+  *sz_out = sz;
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t scan_launch(const ScanLaunch& L, const float* ranges_m, double sigma_m, int32_t* dout) {
+  const ScanTable& t = *L.table;
+  const double h = t.max_range / 256.0;
+  CtArgs ca;
+  int64_t sz = 0;
+  hipError_t e = build_ct(L, ranges_m, ca, &sz);
   if (e != hipSuccess) return e;
 
   ScanArgs a = {};
@@ -699,6 +976,61 @@ hipError_t scan_launch(const ScanLaunch& L, const float* ranges_m, double sigma_
     case 0: hipLaunchKernelGGL(scan_apply_kernel<float>, g2, dim3(kScanThreads), 0, L.stream, a); break;
     case 1: hipLaunchKernelGGL(scan_apply_kernel<__bf16>, g2, dim3(kScanThreads), 0, L.stream, a); break;
     case 2: hipLaunchKernelGGL(scan_apply_kernel<_Float16>, g2, dim3(kScanThreads), 0, L.stream, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t scan_sampled_launch(const ScanLaunch& L, const float* ranges_m, double sigma_m, const uint8_t* mask,
+                               int32_t* list, int32_t* pos) {
+  const ScanTable& t = *L.table;
+  const double h = t.max_range / 256.0;
+  CtArgs ca;
+  int64_t sz = 0;
+  hipError_t e = build_ct(L, ranges_m, ca, &sz);
+  if (e != hipSuccess) return e;
+  SampledArgs a = {};
+  a.rq = t.rq;
+  a.sr = t.sr;
+  a.ct = L.work.c;
+  a.buf[0] = L.buf[0];
+  a.buf[1] = L.buf[1];
+  a.mask = mask;
+  a.list = list;
+  a.pos = pos;
+  a.dsc = reinterpret_cast<int32_t*>(L.scratch);
+  a.partials = L.partials;
+  a.dev = L.dev;
+  a.cells = L.H * L.pitch;
+  a.n_theta = L.n_theta;
+  a.npad = ca.npad;
+  a.kpad = t.kpad;
+  a.W = L.W;
+  a.H = L.H;
+  a.pitch = L.pitch;
+  a.sstride = L.sstride;
+  a.sz = static_cast<int32_t>(sz);
+  a.c64 = h * h / (2.0 * sigma_m * sigma_m);
+  a.c = static_cast<float>(a.c64);
+  a.rq_bytes = static_cast<uint32_t>(t.rq_bytes);
+  a.kchunk = 8;
+  const int g0 = std::min(1024, (a.cells + kCompactThreads - 1) / kCompactThreads);
+  hipLaunchKernelGGL(compact_kernel, dim3(g0), dim3(kCompactThreads), 0, L.stream, a);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  a.p1_blocks = std::min(256, std::max(1, (a.cells + 127) / 128));
+  if (t.f32)
+    hipLaunchKernelGGL(sampled_gemm_kernel<float>, dim3(a.p1_blocks), dim3(kScanThreads), 0, L.stream, a);
+  else
+    hipLaunchKernelGGL(sampled_gemm_kernel<__bf16>, dim3(a.p1_blocks), dim3(kScanThreads), 0, L.stream, a);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  const int ky = (L.n_theta + a.kchunk - 1) / a.kchunk;
+  const int nq = a.cells / 4;
+  const int qx = std::max(1, std::min((nq + kScanThreads - 1) / kScanThreads, kScanApplyBlocks / ky));
+  const dim3 g2(qx, ky);
+  switch (L.dtype) {
+    case 0: hipLaunchKernelGGL(sampled_apply_kernel<float>, g2, dim3(kScanThreads), 0, L.stream, a); break;
+    case 1: hipLaunchKernelGGL(sampled_apply_kernel<__bf16>, g2, dim3(kScanThreads), 0, L.stream, a); break;
+    case 2: hipLaunchKernelGGL(sampled_apply_kernel<_Float16>, g2, dim3(kScanThreads), 0, L.stream, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

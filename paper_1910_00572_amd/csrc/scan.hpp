@@ -26,7 +26,8 @@ struct ScanWork {
   void* c = nullptr;       // [n_theta_pad][kpad] circulant scan operand
 };
 
-// Partials the scan needs: one per 128-cell tile of pass 1, two per pass-2 block.
+// Partials the scan needs: one per 128-cell tile of pass 1, two per pass-2 block
+// (the sampled update needs at most 256 + 2 * 1024).
 inline int kScanMaxBlocks(int W, int H, int pitch) {
   (void)W;
   return static_cast<int>((static_cast<int64_t>(H) * pitch + 127) / 128) + 2048;
@@ -48,6 +49,10 @@ struct ScanLaunch {
 
 // Enqueue the scan update (dout == nullptr) or the diagnostic distance output.
 hipError_t scan_launch(const ScanLaunch& L, const float* ranges_m, double sigma_m, int32_t* dout);
+// Enqueue the sampled update on the cells of `mask` (H x W dense, nonzero =
+// selected).  list and pos: H * pitch int32 each (sample list and positions).
+hipError_t scan_sampled_launch(const ScanLaunch& L, const float* ranges_m, double sigma_m, const uint8_t* mask,
+                               int32_t* list, int32_t* pos);
 size_t scan_work_bytes(int n_theta, int kpad);
 ScanWork scan_work_carve(void* base, int n_theta, int kpad);
 ScanTable scan_table_carve(Carver& c, const mcl_map_desc* d, int pitch, bool f32);

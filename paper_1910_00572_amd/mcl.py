@@ -28,7 +28,8 @@ ABI_SYMBOLS = [
     "mcl_last_error", "mcl_map_workspace_bytes", "mcl_map_create", "mcl_map_destroy",
     "mcl_filter_workspace_bytes", "mcl_init_belief", "mcl_filter_destroy", "mcl_step_odometry",
     "mcl_apply_scan", "mcl_normalize", "mcl_read_belief", "mcl_export_belief", "mcl_scan_sqdist",
-    "mcl_get_info", "mcl_step_batch", "mcl_batch_workspace_bytes",
+    "mcl_get_info", "mcl_step_batch", "mcl_batch_workspace_bytes", "mcl_sample_cells",
+    "mcl_apply_scan_sampled", "mcl_dither",
 ]
 
 
@@ -114,6 +115,12 @@ def load_library(path: str = _LIB_PATH):
     lib.mcl_step_batch.argtypes = [POINTER(c_void_p), c_void_p, c_int32, c_void_p, c_size_t, c_void_p]
     lib.mcl_batch_workspace_bytes.restype = c_size_t
     lib.mcl_batch_workspace_bytes.argtypes = [c_int32]
+    lib.mcl_sample_cells.restype = c_int
+    lib.mcl_sample_cells.argtypes = [c_void_p, c_int32, c_void_p]
+    lib.mcl_apply_scan_sampled.restype = c_int
+    lib.mcl_apply_scan_sampled.argtypes = [c_void_p, c_void_p, c_int32, c_double, c_void_p]
+    lib.mcl_dither.restype = c_int
+    lib.mcl_dither.argtypes = [c_void_p, c_int32, c_int32, c_void_p, c_void_p]
     _lib = lib
     return lib
 
@@ -254,6 +261,22 @@ class Filter:
         _check(_lib.mcl_scan_sqdist(self.handle, z.ctypes.data, len(z), c_void_p(out.data_ptr())))
         return out
 
+    def sample_cells(self, n_samples, out=None):
+        """Floyd-Steinberg sample mask of the belief map: uint8 CUDA tensor (H, W)."""
+        import torch
+        if out is None:
+            out = torch.empty((self.map.height, self.map.width), dtype=torch.uint8, device="cuda")
+        _check(_lib.mcl_sample_cells(self.handle, int(n_samples), c_void_p(out.data_ptr())))
+        return out
+
+    def apply_scan_sampled(self, ranges_m, sigma_m, mask):
+        """Observation update on the states of the cells of `mask` (uint8 CUDA tensor (H, W))."""
+        assert mask.dtype.itemsize == 1 and mask.is_contiguous() and mask.is_cuda
+        assert tuple(mask.shape) == (self.map.height, self.map.width)
+        z = np.ascontiguousarray(ranges_m, dtype=np.float32)
+        _check(_lib.mcl_apply_scan_sampled(self.handle, z.ctypes.data, len(z), float(sigma_m),
+                                           c_void_p(mask.data_ptr())))
+
     def info(self, sync=True) -> Info:
         inf = Info()
         _check(_lib.mcl_get_info(self.handle, int(sync), byref(inf)))
@@ -280,6 +303,26 @@ def normalize(f: Filter) -> float:
 
 def read_belief(f: Filter, want_belief=True):
     return f.read_belief(want_belief)
+
+
+def sample_cells(f: Filter, n_samples, out=None):
+    return f.sample_cells(n_samples, out)
+
+
+def apply_scan_sampled(f: Filter, ranges_m, sigma_m, mask):
+    f.apply_scan_sampled(ranges_m, sigma_m, mask)
+
+
+def dither(intensity, out=None, stream=None):
+    """Floyd-Steinberg mask (uint8 CUDA tensor) of a float32 CUDA image (H, W)."""
+    import torch
+    assert intensity.dtype == torch.float32 and intensity.is_contiguous() and intensity.is_cuda
+    H, W = intensity.shape
+    if out is None:
+        out = torch.empty((H, W), dtype=torch.uint8, device=intensity.device)
+    _check(load_library().mcl_dither(c_void_p(intensity.data_ptr()), int(W), int(H), c_void_p(out.data_ptr()),
+                                     _stream_handle(stream)))
+    return out
 
 
 class BatchWorkspace:

@@ -1,0 +1,344 @@
+"""Floyd-Steinberg sample selection and the sampled scan update on the GPU vs the oracle.
+
+GPU only; every call goes through the C ABI.
+
+Dithering turns FP32 arithmetic into integers (selected or not), and the
+kernel carries it out in the oracle's order, so masks are compared bit for
+bit: the kernel against the oracle's raster loop (its C form for large
+images) on the same seeded intensities, at sizes that reach every launch
+shape (one and two rows per thread with three-step phases, four rows per
+thread with one-step phases) and ragged edges.  The belief-map intensity is
+compared bit for bit on beliefs whose values make both sides' intensities
+exact (small integers whose sum is a power of two, so normalising is exact);
+on general beliefs the two intensities differ by FP32 rounding, which moves
+the dithering pattern, and only the selected counts are compared.
+
+The sampled update is given the oracle's mask (dithered from the oracle's
+belief) and compared with the oracle's update to the tolerance of the dense
+scan update, whose arithmetic it shares (the factor exp(-c (D - D*)) with D
+exact and c (D - D*) formed in FP32).
+"""
+
+import zlib
+
+import numpy as np
+import pytest
+
+import oracle as O
+from gen import bsp_rooms, noisy_scan, random_odometry, range_table, rooms_and_corridors, smooth_trajectory
+from tests.gpu_harness import in_tie_set, make_gpu, needs_gpu, oracle_params, peak_err, say
+
+pytestmark = [pytest.mark.gpu, needs_gpu]
+
+SCAN_PEAK_TOL = 2e-5
+
+
+def _seed(*key):
+    return zlib.crc32(repr(key).encode())
+
+
+def _intensity(shape, dist, seed):
+    rng = np.random.default_rng(seed)
+    if dist == "uniform":
+        img = rng.uniform(0, 1, shape)
+    elif dist == "cubed":
+        img = rng.uniform(0, 1, shape) ** 3
+    elif dist == "near_half":
+        img = 0.5 + rng.integers(-3, 4, shape) * 2.0 ** -24
+    elif dist == "blobs":
+        # a belief-like intensity: a few bright blobs on a faint floor
+        H, W = shape
+        yy, xx = np.mgrid[0:H, 0:W]
+        img = np.full(shape, 1e-4)
+        for _ in range(4):
+            cy, cx = rng.uniform(0, H), rng.uniform(0, W)
+            r = rng.uniform(1, 2 + max(H, W) / 6)
+            img += np.exp(-((yy - cy) ** 2 + (xx - cx) ** 2) / (2 * r * r))
+        img = np.minimum(1.0, img * (0.02 * H * W) / img.sum())
+    else:
+        img = rng.uniform(-0.5, 2.0, shape)
+    return img.astype(np.float32)
+
+
+def _gpu_dither(img):
+    import torch
+    from paper_1910_00572_amd import mcl
+    t = torch.from_numpy(np.ascontiguousarray(img)).cuda()
+    out = mcl.dither(t)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+SMALL_SHAPES = [(1, 1), (1, 50), (50, 1), (3, 2), (37, 53), (64, 64), (129, 300), (300, 129), (512, 512)]
+
+
+@pytest.mark.parametrize("shape", SMALL_SHAPES, ids=lambda s: f"{s[0]}x{s[1]}")
+@pytest.mark.parametrize("dist", ["uniform", "cubed", "near_half", "blobs", "wide"])
+def test_dither_is_bit_exact(shape, dist):
+    img = _intensity(shape, dist, _seed(shape, dist))
+    say(f"[dither] {shape} {dist}")
+    got = _gpu_dither(img)
+    assert np.array_equal(got, O.floyd_steinberg_c(img))
+    if shape[0] * shape[1] <= 4096:
+        assert np.array_equal(got, O.floyd_steinberg(img))
+
+
+@pytest.mark.parametrize("shape", [(1100, 4200), (2100, 8200)], ids=["two_rows_per_thread", "four_rows_one_step"])
+def test_dither_is_bit_exact_large(shape):
+    # (1100, 4200): three-step phases with two rows per thread; (2100, 8200):
+    # the three-step ring does not fit, one-step phases with four rows per thread
+    img = _intensity(shape, "blobs", _seed(shape))
+    say(f"[dither] large {shape}")
+    assert np.array_equal(_gpu_dither(img), O.floyd_steinberg_c(img))
+
+
+def test_dither_sizes_and_errors():
+    import torch
+    from paper_1910_00572_amd import mcl
+    lib = mcl.load_library()
+    dummy = torch.zeros(16, dtype=torch.float32, device="cuda")
+    m = torch.zeros(16, dtype=torch.uint8, device="cuda")
+    from ctypes import c_void_p
+    s = c_void_p(torch.cuda.current_stream().cuda_stream)
+    assert lib.mcl_dither(c_void_p(dummy.data_ptr()), 0, 5, c_void_p(m.data_ptr()), s) == mcl.OK
+    assert lib.mcl_dither(c_void_p(dummy.data_ptr()), 5, 0, c_void_p(m.data_ptr()), s) == mcl.OK
+    assert lib.mcl_dither(c_void_p(dummy.data_ptr()), -1, 5, c_void_p(m.data_ptr()), s) == mcl.EINVAL
+    assert lib.mcl_dither(None, 4, 4, c_void_p(m.data_ptr()), s) == mcl.EINVAL
+    assert lib.mcl_dither(c_void_p(dummy.data_ptr()), 4, 4, None, s) == mcl.EINVAL
+    # min(H, W / 2 + 1) above 4096: the error ring would not fit (checked before any launch)
+    assert lib.mcl_dither(c_void_p(dummy.data_ptr()), 10000, 5000, c_void_p(m.data_ptr()), s) == mcl.EINVAL
+    torch.cuda.synchronize()
+
+
+# ---- belief map -> intensity -> mask ------------------------------------------------
+
+def _dyadic_belief(occ, n_theta, seed, vmax=255):
+    """Integer values (exact in every storage type) on free states, summing to a power of two."""
+    rng = np.random.default_rng(seed)
+    H, W = occ.shape
+    v = np.zeros((n_theta, H, W), np.float64)
+    free = np.argwhere(occ == 0)
+    pick = free[rng.choice(len(free), len(free) // 2, replace=False)]
+    ks = rng.integers(0, n_theta, len(pick))
+    v[ks, pick[:, 0], pick[:, 1]] = rng.integers(0, vmax + 1, len(pick))
+    total = int(v.sum())
+    p = int(np.ceil(np.log2(total + 1))) + 1
+    rest = 2 ** p - total
+    j = 0
+    while rest > 0:  # fill up to 2^p on further free states, vmax at a time
+        jj, ii = free[j % len(free)]
+        k = j % n_theta
+        add = min(rest, vmax - int(v[k, jj, ii]))
+        v[k, jj, ii] += add
+        rest -= add
+        j += 1
+    assert int(v.sum()) == 2 ** p
+    return v.astype(np.float32), 2 ** p
+
+
+@pytest.mark.parametrize("storage", ["f32", "bf16", "f16"])
+def test_sample_cells_exact_on_dyadic_belief(storage):
+    occ = bsp_rooms(96, 80, seed=71)
+    v, total = _dyadic_belief(occ, 8, seed=72)
+    _, f = make_gpu(occ, 0.1, 8, 0.6, 0.6, storage=storage, init=v)
+    B = v.astype(np.float64) / total  # exact: the total is a power of two
+    for n in (0, 1, 37, 300, 5000):
+        say(f"[sample] dyadic {storage} n={n}")
+        got = f.sample_cells(n).cpu().numpy()
+        ref = O.sample_mask(B, n)
+        assert np.array_equal(got, ref), (n, int(got.sum()), int(ref.sum()))
+
+
+def test_sample_cells_count_after_motion():
+    occ = bsp_rooms(128, 112, seed=73)
+    n_theta = 12
+    _, f = make_gpu(occ, 0.1, n_theta, 0.7, 0.7)
+    p = oracle_params(n_theta, 0.1, 0.7, 0.7)
+    st = O.init_uniform(occ, n_theta)
+    for u, v, w in random_odometry(12, seed=74):
+        f.step_odometry(u, v, w)
+        st = O.step(st, occ, p, u, v, w)
+    for n in (50, 400, 3000):
+        got = f.sample_cells(n).cpu().numpy()
+        I = O.dither_intensity(O.belief_map(st.B), n)
+        ref = O.floyd_steinberg(I)
+        say(f"[sample] after motion n={n}: gpu {int(got.sum())} oracle {int(ref.sum())} sum I {float(I.sum()):.1f}")
+        # the intensities differ by FP32 rounding only; both selections follow sum I
+        assert abs(int(got.sum()) - int(ref.sum())) <= max(3, 0.02 * n)
+
+
+# ---- sampled update -------------------------------------------------------------------
+
+def _setup(occ, cell, n_dirs, max_range, n_theta, sxy=0.7, sth=0.7, flags=3, init=None, storage="f32"):
+    R = range_table(occ, cell, n_dirs, max_range)
+    m, f = make_gpu(occ, cell, n_theta, sxy, sth, flags=flags, range_table=R, max_range_m=max_range, init=init,
+                    storage=storage)
+    return R, m, f
+
+
+def _to_gpu(mask):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(mask, dtype=np.uint8)).cuda()
+
+
+def _ln_tol(st_ref):
+    return 1e-5 + 1e-6 * abs(st_ref.log_norm)
+
+
+@pytest.mark.parametrize("f32_ops", [False, True])
+def test_sampled_update_matches_oracle_with_motion(f32_ops):
+    occ = bsp_rooms(64, 56, seed=75)
+    n_theta = 16
+    flags = 3 | (8 if f32_ops else 0)
+    R, m, f = _setup(occ, 0.1, 90, 4.0, n_theta, flags=flags)
+    p = oracle_params(n_theta, 0.1, 0.7, 0.7, flags=3)
+    Rq = O.quantize_ranges(R, 4.0)
+    st = O.init_uniform(occ, n_theta)
+    free = np.argwhere(occ == 0)
+    rng = np.random.default_rng(76)
+    for t, (u, v, w) in enumerate(random_odometry(30, seed=77)):
+        f.step_odometry(u, v, w)
+        st = O.step(st, occ, p, u, v, w)
+        if t % 10 == 9:
+            j, i = free[rng.integers(len(free))]
+            z = noisy_scan(occ, 0.1, ((i + 0.5) * 0.1, (j + 0.5) * 0.1, rng.uniform(-3, 3)), 90, 4.0, 0.1,
+                           seed=t)
+            mask = O.sample_mask(st.B, 150)
+            f.apply_scan_sampled(z, 0.15, _to_gpu(mask))
+            st = O.apply_scan_sampled(st, Rq, O.quantize_ranges(z, 4.0), 0.15, 4.0, mask)
+            b, pose, _, ln = f.read_belief()
+            err = peak_err(b, st.B)
+            say(f"[sampled] step {t} f32_ops={f32_ops} samples {int(mask.sum())} peak-normalised error "
+                f"{err:.3e} log_norm {ln:.6f} vs {st.log_norm:.6f}")
+            assert err <= SCAN_PEAK_TOL
+            assert in_tie_set(pose.as_tuple(), st.B, 1e-5)
+            assert abs(ln - st.log_norm) <= _ln_tol(st)
+
+
+def _smooth_init(occ, n_theta, seed):
+    rng = np.random.default_rng(seed)
+    H, W = occ.shape
+    yy, xx = np.mgrid[0:H, 0:W]
+    b = np.zeros((n_theta, H, W))
+    for k in range(n_theta):
+        cy, cx = rng.uniform(0, H), rng.uniform(0, W)
+        r = rng.uniform(3, 1 + max(H, W) / 4)
+        b[k] = np.exp(-((yy - cy) ** 2 + (xx - cx) ** 2) / (2 * r * r)) + 1e-3
+    b *= (occ == 0)[None]
+    return b.astype(np.float32)
+
+
+@pytest.mark.parametrize("kind", ["empty", "one", "ragged33", "full", "dither"])
+def test_sampled_update_edge_masks(kind):
+    occ = bsp_rooms(70, 45, seed=78)
+    n_theta = 10
+    init = _smooth_init(occ, n_theta, seed=79)
+    R, m, f = _setup(occ, 0.1, 64, 3.5, n_theta, init=init)
+    B = init.astype(np.float64) / init.astype(np.float64).sum()
+    st = O.FilterState(B=B)
+    Rq = O.quantize_ranges(R, 3.5)
+    free = np.argwhere(occ == 0)
+    rng = np.random.default_rng(80)
+    j, i = free[len(free) // 2]
+    z = noisy_scan(occ, 0.1, ((i + 0.5) * 0.1, (j + 0.5) * 0.1, 0.9), 64, 3.5, 0.05, seed=81)
+    mask = np.zeros(occ.shape, np.uint8)
+    if kind == "one":
+        mask[j, i] = 1
+    elif kind == "ragged33":
+        pick = rng.choice(occ.size, 33, replace=False)
+        mask.reshape(-1)[pick] = 1
+    elif kind == "full":
+        mask[:] = 1
+    elif kind == "dither":
+        mask = O.sample_mask(B, 200)
+    before, _, _, ln0 = f.read_belief()
+    f.apply_scan_sampled(z, 0.1, _to_gpu(mask))
+    ref = O.apply_scan_sampled(st, Rq, O.quantize_ranges(z, 3.5), 0.1, 3.5, mask)
+    b, pose, _, ln = f.read_belief()
+    say(f"[sampled] {kind}: {int(mask.sum())} cells, error {peak_err(b, ref.B):.3e}, ln {ln:.6f} vs "
+        f"{ref.log_norm:.6f}")
+    if kind == "empty":
+        assert np.array_equal(b, before) and ln == ln0
+    assert peak_err(b, ref.B) <= SCAN_PEAK_TOL
+    assert abs(ln - ref.log_norm) <= _ln_tol(ref)
+    # the update can be repeated with a new mask (sample list and counters reset)
+    f.apply_scan_sampled(z, 0.1, _to_gpu(mask))
+    ref2 = O.apply_scan_sampled(ref, Rq, O.quantize_ranges(z, 3.5), 0.1, 3.5, mask)
+    b2, _, _, ln2 = f.read_belief()
+    assert peak_err(b2, ref2.B) <= SCAN_PEAK_TOL
+    assert abs(ln2 - ref2.log_norm) <= _ln_tol(ref2)
+
+
+def test_sampled_update_degenerate_keeps_belief():
+    # all mass on one cell, sampled together with a massless cell the scan
+    # fits exactly: with a tiny sigma every massive state underflows
+    from paper_1910_00572_amd import mcl
+    occ = bsp_rooms(40, 36, seed=82)
+    n_theta = 6
+    free = np.argwhere(occ == 0)
+    (ja, ia), (jb, ib) = free[3], free[-4]
+    init = np.zeros((n_theta, 36, 40), np.float32)
+    init[:, ja, ia] = 1.0
+    R, m, f = _setup(occ, 0.1, 48, 3.0, n_theta, init=init)
+    z = noisy_scan(occ, 0.1, ((ib + 0.5) * 0.1, (jb + 0.5) * 0.1, 0.0), 48, 3.0, 0.0, seed=83)
+    mask = np.zeros(occ.shape, np.uint8)
+    mask[ja, ia] = mask[jb, ib] = 1
+    Rq = O.quantize_ranges(R, 3.0)
+    st = O.FilterState(B=init.astype(np.float64) / n_theta)
+    ref = O.apply_scan_sampled(st, Rq, O.quantize_ranges(z, 3.0), 0.001, 3.0, mask)
+    assert ref.degenerate
+    before, _, _, _ = f.read_belief()
+    f.apply_scan_sampled(z, 0.001, _to_gpu(mask))
+    with pytest.raises(mcl.MclError) as ei:
+        f.read_belief()
+    assert ei.value.status == mcl.EDEGENERATE
+    kept = ei.value.readout[0]
+    assert np.array_equal(kept, before)
+
+
+def test_sampled_update_full_size():
+    # 512 x 512 cells, 72 channels, 360 beams, about 4096 samples
+    occ = rooms_and_corridors(512, 512, seed=3)
+    n_theta = 72
+    init = _smooth_init(occ, n_theta, seed=84)
+    R, m, f = _setup(occ, 0.05, 360, 10.0, n_theta, sxy=1.0, sth=1.0, init=init)
+    B = init.astype(np.float64) / init.astype(np.float64).sum()
+    mask = O.floyd_steinberg_c(O.dither_intensity(O.belief_map(B), 4096))
+    poses, _ = smooth_trajectory(occ, 0.05, 1, seed=4)
+    z = noisy_scan(occ, 0.05, poses[0], 360, 10.0, 0.1, seed=85)
+    say(f"[sampled] full size, {int(mask.sum())} samples")
+    f.apply_scan_sampled(z, 0.1, _to_gpu(mask))
+    ref = O.apply_scan_sampled(O.FilterState(B=B), O.quantize_ranges(R, 10.0), O.quantize_ranges(z, 10.0), 0.1,
+                               10.0, mask)
+    b, pose, _, ln = f.read_belief()
+    err = peak_err(b, ref.B)
+    say(f"[sampled] full size error {err:.3e} ln {ln:.6f} vs {ref.log_norm:.6f}")
+    assert err <= SCAN_PEAK_TOL
+    assert abs(ln - ref.log_norm) <= _ln_tol(ref)
+
+
+def test_sample_then_update_scales_unsampled_states_uniformly():
+    # the whole GPU pipeline (mask from the GPU belief): unsampled states all
+    # keep one common ratio to their prior, sampled ones never exceed it
+    occ = bsp_rooms(80, 64, seed=86)
+    n_theta = 12
+    R, m, f = _setup(occ, 0.1, 72, 3.0, n_theta)
+    for u, v, w in random_odometry(8, seed=87):
+        f.step_odometry(u, v, w)
+    prior, _, _, _ = f.read_belief()
+    mask_t = f.sample_cells(250)
+    mask = mask_t.cpu().numpy().astype(bool)
+    free = np.argwhere(occ == 0)
+    j, i = free[len(free) // 3]
+    z = noisy_scan(occ, 0.1, ((i + 0.5) * 0.1, (j + 0.5) * 0.1, 0.3), 72, 3.0, 0.1, seed=88)
+    f.apply_scan_sampled(z, 0.2, mask_t)
+    post, _, _, _ = f.read_belief()
+    live = prior > prior.max() * 1e-6
+    samp = np.broadcast_to(mask, prior.shape)
+    ratio = post[live].astype(np.float64) / prior[live]
+    r_uns = ratio[~samp[live]]
+    r_smp = ratio[samp[live]]
+    say(f"[sampled] pipeline: {int(mask.sum())} cells, unsampled ratio spread {r_uns.max() / r_uns.min() - 1:.2e}")
+    assert 100 <= mask.sum() <= 400
+    assert r_uns.max() / r_uns.min() - 1 <= 1e-5
+    assert r_smp.max() <= r_uns.min() * (1 + 1e-5)

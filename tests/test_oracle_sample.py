@@ -9,6 +9,7 @@ none it changes nothing; samples never gain mass relative to the rest.
 """
 
 import os
+import zlib
 
 import numpy as np
 import pytest
@@ -141,3 +142,33 @@ def test_samples_never_gain_relative_to_the_rest():
     unsampled = ~np.broadcast_to(mask.astype(bool), st.B.shape) & (st.B > 0)
     assert ratio[sampled].max() <= ratio[unsampled].min() * (1 + 1e-12)
     assert abs(out.B.sum() - 1.0) < 1e-12
+
+
+# ---- the C form of the dithering oracle (large images) ---------------------------
+
+@pytest.mark.parametrize("case", _golden(), ids=lambda c: c[0])
+def test_c_form_hand_derived_selections(case):
+    _, img, sel = case
+    assert np.array_equal(O.floyd_steinberg_c(img), sel)
+
+
+@pytest.mark.parametrize("shape", [(1, 1), (1, 29), (31, 1), (2, 2), (17, 23), (40, 64)])
+@pytest.mark.parametrize("dist", ["uniform", "cubed", "near_half", "wide"])
+def test_c_form_equals_python_form(shape, dist):
+    # bit-for-bit equality with the pinned raster loop over value mixes that
+    # exercise the threshold, negative errors and intensities above one
+    rng = np.random.default_rng(zlib.crc32(repr((shape, dist)).encode()))
+    if dist == "uniform":
+        img = rng.uniform(0, 1, shape)
+    elif dist == "cubed":
+        img = rng.uniform(0, 1, shape) ** 3
+    elif dist == "near_half":
+        img = 0.5 + rng.integers(-3, 4, shape) * np.float32(2.0 ** -24)
+    else:
+        img = rng.uniform(-0.5, 2.0, shape)
+    img = img.astype(np.float32)
+    assert np.array_equal(O.floyd_steinberg_c(img), O.floyd_steinberg(img))
+
+
+def test_c_form_empty_image():
+    assert O.floyd_steinberg_c(np.zeros((0, 5), np.float32)).shape == (0, 5)
