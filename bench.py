@@ -1,6 +1,6 @@
 """Benchmark of the dense belief-tensor odometry step on one MI355X.
 
-python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--only NAME]
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-extra] [--only a,b]
 
 Headline workload: a 512x512 synthetic floor plan (0.05 m cells, rooms,
 corridors and clutter, ~35 % occupied) with 72 heading bins (18.9 M states),
@@ -184,6 +184,62 @@ def bench_scan(n_scans):
     return out
 
 
+def bench_sampled(n_scans, n_samples=4096):
+    """512x512 map, 72 bins, 360 beams: Floyd-Steinberg sample selection and the sampled update."""
+    import torch
+    from gen import noisy_scan, range_table, rooms_and_corridors, smooth_trajectory
+    from paper_1910_00572_amd import mcl
+    occ = rooms_and_corridors(512, 512, seed=3)
+    poses, odo = smooth_trajectory(occ, 0.05, 200, seed=4)
+    R = range_table(occ, 0.05, 360, 10.0)
+    m = mcl.Map(occ, 0.05, 1.0, range_table=R, max_range_m=10.0)
+    f = mcl.Filter(m, 72, 1.0, storage="f32")
+    zs = [noisy_scan(occ, 0.05, poses[(10 * t) % 200], 360, 10.0, 0.1, seed=7 + t) for t in range(n_scans)]
+    mask = torch.empty((512, 512), dtype=torch.uint8, device="cuda")
+    # a multimodal belief: motion from the uniform start, then a few sampled scans
+    for t in range(30):
+        f.step_odometry(*odo[t])
+        if t % 10 == 9:
+            f.sample_cells(n_samples, out=mask)
+            f.apply_scan_sampled(zs[t // 10], 0.1, mask)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in zs]
+    counts = []
+    for t, z in enumerate(zs):
+        ev[t][0].record(stream)
+        f.sample_cells(n_samples, out=mask)
+        ev[t][1].record(stream)
+        f.apply_scan_sampled(z, 0.1, mask)
+        ev[t][2].record(stream)
+        if t == len(zs) - 1:
+            counts.append(int(mask.sum().item()))
+    torch.cuda.synchronize()
+    sel_ms = float(np.mean([a.elapsed_time(b) for a, b, _ in ev]))
+    upd_ms = float(np.mean([b.elapsed_time(c) for _, b, c in ev]))
+    phases = (511 + 4 * 511) // 3 + 1  # wavefront phases of three steps on a 512 x 512 map
+    # steps with a sampled scan every 10 steps, 100 steps
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for t in range(100):
+        f.step_odometry(*odo[30 + t])
+        if t % 10 == 9:
+            f.sample_cells(n_samples, out=mask)
+            f.apply_scan_sampled(zs[(t // 10) % len(zs)], 0.1, mask)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    states = 512 * 512 * 72
+    out = {"n_samples_requested": n_samples, "cells_selected": counts[0],
+           "select_ms": sel_ms, "update_ms": upd_ms,
+           "select_plus_update_ms": sel_ms + upd_ms,
+           "dither_phases": phases,
+           "belief_read_bytes_select": states * 4, "belief_read_bytes_update": states * 4,
+           "steps_with_sampled_scan_every_10_states_steps_per_s": states * 100 / dt}
+    del f, m
+    torch.cuda.empty_cache()
+    return out
+
+
 def bench_serving(n_requests, seed=8, capacity=None):
     """Poisson stream of mixed filters (grid 128..1024, 36/72 bins, FP32/BF16, scans on half).
 
@@ -241,6 +297,8 @@ def main():
     ap.add_argument("--calibration-copy-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
     ap.add_argument("--serving-requests", type=int, default=256)
+    ap.add_argument("--only", default="", help="comma-separated extra sections to run "
+                    "(mixed, scan, sampled, serving); default all")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: the filter step is a single-GPU kernel and this build "
@@ -305,11 +363,17 @@ def main():
     del f, m
     torch.cuda.empty_cache()
     if not args.no_extra:
-        log("[bench] 1024x1024x128 FP32 vs BF16")
-        out["mixed_precision_1024x1024x128"] = bench_mixed_precision(100)
-        log("[bench] scan update 512x512x72, 360 beams")
-        out["scan_512x512x72_360beams"] = bench_scan(20)
-        if args.serving_requests > 0:
+        only = set(x for x in args.only.split(",") if x) or {"mixed", "scan", "sampled", "serving"}
+        if "mixed" in only:
+            log("[bench] 1024x1024x128 FP32 vs BF16")
+            out["mixed_precision_1024x1024x128"] = bench_mixed_precision(100)
+        if "scan" in only:
+            log("[bench] scan update 512x512x72, 360 beams")
+            out["scan_512x512x72_360beams"] = bench_scan(20)
+        if "sampled" in only:
+            log("[bench] sampled update 512x512x72, 360 beams, 4096 samples")
+            out["sampled_scan_512x512x72_360beams"] = bench_sampled(20)
+        if "serving" in only and args.serving_requests > 0:
             log(f"[bench] serving {args.serving_requests} requests")
             out["serving"] = bench_serving(args.serving_requests, capacity=value)
     if not args.no_cpu_baseline:

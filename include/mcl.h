@@ -218,7 +218,7 @@ mcl_status mcl_apply_scan_sampled(mcl_filter f, const float* ranges_m, int32_t n
  * order; every product and sum is FP32 rounded to nearest, no fused
  * multiply-add.  `stream` is a hipStream_t (NULL = default stream).  A zero
  * width or height does nothing.  EINVAL for negative sizes, NULL pointers,
- * W * H >= 2^29, or min(H, W / 2 + 1) above 4096 (the error ring of the
+ * W * H >= 2^29, or H >= 4096 together with W >= 8190 (the error ring of the
  * wavefront kernel lives in 64 KB of LDS). */
 mcl_status mcl_dither(const float* dev_intensity, int32_t width, int32_t height, uint8_t* dev_mask,
                       void* stream);

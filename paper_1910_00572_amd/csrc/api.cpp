@@ -282,7 +282,7 @@ size_t carve_filter(mcl_filter f, void* ws, const mcl_map m, const mcl_params* p
   const StepShape sh = choose_shape(m->W, m->H, p->n_theta, R, eb);
   const int np = std::max(sh.blocks(), std::max(kReduceBlocks, kScanMaxBlocks(m->W, m->H, m->pitch)));
   double* partials = static_cast<double*>(c.take(static_cast<size_t>(np) * 3 * sizeof(double)));
-  FilterDev* dev = static_cast<FilterDev*>(c.take(sizeof(FilterDev)));
+  FilterDev* dev = static_cast<FilterDev*>(c.take(kDevRegionBytes));
   float* scratch = nullptr;
   int32_t* samp = nullptr;
   if (m->scan.n_dirs > 0) {
@@ -671,7 +671,7 @@ mcl_status mcl_sample_cells(mcl_filter f, int32_t n_samples, uint8_t* dev_mask) 
   if (n_samples < 0) return fail(MCL_EINVAL, "n_samples must be >= 0");
   const mcl_map m = f->map;
   if (!dither_supported(m->W, m->H))
-    return fail(MCL_EINVAL, "a %d x %d map is beyond the dithering kernel (min(H, W/2 + 1) too large)", m->W, m->H);
+    return fail(MCL_EINVAL, "a %d x %d map is beyond the dithering kernel (H >= 4096 and W >= 8190)", m->W, m->H);
   HIP_TRY(launch_dither_source(f->dtype, f->buf[0], f->buf[1], m->W, m->H, m->pitch, f->T, f->sstride, f->partials,
                                f->dev, f->staging, f->stream),
           "belief map");
@@ -685,8 +685,8 @@ mcl_status mcl_dither(const float* dev_intensity, int32_t width, int32_t height,
   if (width == 0 || height == 0) return MCL_OK;
   if (!dev_intensity || !dev_mask) return fail(MCL_EINVAL, "NULL image or mask");
   if (!dither_supported(width, height))
-    return fail(MCL_EINVAL, "a %d x %d image is beyond the dithering kernel (min(H, W/2 + 1) too large)", width,
-                height);
+    return fail(MCL_EINVAL, "a %d x %d image is beyond the dithering kernel (H >= 4096 and W >= 8190, or W * H >= 2^29)",
+                width, height);
   HIP_TRY(launch_dither(dev_intensity, width, height, dev_mask, false, 1.f, nullptr,
                         static_cast<hipStream_t>(stream)),
           "dithering");

@@ -137,11 +137,10 @@ __global__ __launch_bounds__(kRedThreads) void reduce_kernel(ReduceArgs a) {
     __syncthreads();
   }
   if (t == 0) {
-    a.partials[3 * blockIdx.x] = rs[0];
-    a.partials[3 * blockIdx.x + 1] = static_cast<double>(rm[0]);
-    a.partials[3 * blockIdx.x + 2] = static_cast<double>(ri[0]);
-    const uint32_t prev = __hip_atomic_fetch_add(&dev->counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    last_flag = (prev == static_cast<uint32_t>(nblk - 1));
+    publish(&a.partials[3 * blockIdx.x], rs[0]);
+    publish(&a.partials[3 * blockIdx.x + 1], static_cast<double>(rm[0]));
+    publish(&a.partials[3 * blockIdx.x + 2], static_cast<double>(ri[0]));
+    last_flag = arrive_last(dev, blockIdx.x, static_cast<uint32_t>(nblk));
   }
   __syncthreads();
   if (!last_flag) return;
@@ -240,6 +239,8 @@ __global__ void dev_init_kernel(FilterDev* dev, double sum, float maxval) {
   d.counter = 0;
   d.argmax_idx = -1;
   *dev = d;
+  uint32_t* cg = reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(dev) + kDevBytes);
+  for (int i = 0; i < kArriveGroups * kArriveStride; ++i) cg[i] = 0u;
 }
 
 template <typename T>

@@ -44,19 +44,23 @@ constexpr int ring_cols(int K) {
 }
 
 struct DitherArgs {
-  const float* src;     // H x W dense: intensity, or the belief map (scaled)
+  const float* src;     // H x W dense intensity
   uint8_t* mask;        // H x W dense output, 1 = selected
-  const FilterDev* dev; // scaled: the FP32 total of the belief map
   int32_t W, H;
   int32_t ring;         // rows of the error ring (power of two)
-  int32_t scaled;
-  float n;              // requested sample count (scaled)
   int32_t phases;       // phases to run (a multiple of the prefetch depth)
   uint32_t cells;       // W * H
 };
 
 // One thread per row slot; slot s of thread t holds rows t + nt (s + MAXA q).
-// PF = phases between the load of a source value and its use.
+// PF = phases between the load of an intensity and its use.
+//
+// Borders cost no tests: error from outside the image is an exact zero in
+// the ring (row -1 is a ring row that stays zero until row 0 is done; each
+// row writes zero to its column -1 in the phase that holds it and to column
+// W when it ends; the left error is reset when a slot takes a new row).  Adding a zero
+// changes no nonzero sum and a zero's sign changes no decision, so the
+// selection is the one that skips those terms.
 template <int K, int MAXA, int PF>
 __global__ __launch_bounds__(kDitherMaxThreads) void dither_kernel(DitherArgs a) {
 #pragma clang fp contract(off)
@@ -67,12 +71,6 @@ __global__ __launch_bounds__(kDitherMaxThreads) void dither_kernel(DitherArgs a)
   const int rmask = a.ring - 1;
   const int span = nt * MAXA;        // rows between consecutive rows of one slot
   const int wrap = (K + 1) * span;   // columns a slot moves back when it takes its next row
-  // unscaled: I = img exactly (1 * img / 1); a non-positive total gives I = 0
-  const float total_in = a.scaled ? a.dev->dither_total : 1.f;
-  const bool tpos = total_in > 0.f;
-  const float total = tpos ? total_in : 1.f;
-  const float nsamp = a.scaled ? a.n : 1.f;
-  const bool clamp = a.scaled != 0;
   const float w7 = 7.f / 16.f, w3 = 3.f / 16.f, w5 = 5.f / 16.f, w1 = 1.f / 16.f;
   // Offsets past the end of a buffer read zero and drop stores, so loads and
   // stores of cells outside the image need no branch.
@@ -82,37 +80,44 @@ __global__ __launch_bounds__(kDitherMaxThreads) void dither_kernel(DitherArgs a)
       a.mask, static_cast<short>(0), static_cast<int>(a.cells), 0x00020000);
   constexpr uint32_t kOut = 0x80000000u;  // at or past the end of both buffers
 
+  for (int x = t; x < a.ring * D; x += nt) ering[x] = 0.f;
+
   int row[MAXA], col[MAXA];    // current row and first column of the phase
   int prow[MAXA], pcol[MAXA];  // the same, PF phases ahead (loads in flight)
   float eleft[MAXA];           // error of the previous cell of the row
-  float pf[PF][MAXA][K];       // source values, loaded PF phases ahead
+  float pf[PF][MAXA][K];       // intensities, loaded PF phases ahead
 #pragma unroll
   for (int s = 0; s < MAXA; ++s) {
     row[s] = prow[s] = t + nt * s;
     col[s] = pcol[s] = -(K + 1) * row[s];
     eleft[s] = 0.f;
   }
-  auto advance = [&](int& r, int& c) {
+  // a row is done once its phase starts past column W (column W itself is
+  // still visited, to write the zero the row below reads there)
+  auto advance = [&](int& r, int& c) -> bool {
     c += K;
-    const bool done = c >= W;
+    const bool done = c > W;
     r = done ? r + span : r;
     c = done ? c - wrap : c;
+    return done;
   };
   auto load_phase = [&](float (&dst)[MAXA][K]) {
 #pragma unroll
     for (int s = 0; s < MAXA; ++s) {
+      const uint32_t rb = static_cast<uint32_t>(prow[s]) * static_cast<uint32_t>(W);
 #pragma unroll
       for (int c = 0; c < K; ++c) {
         const int i = pcol[s] + c;
         const bool ok = i >= 0 && i < W && prow[s] < H;
         dst[s][c] = __builtin_bit_cast(
-            float, __builtin_amdgcn_raw_buffer_load_b32(rsrc, ok ? static_cast<uint32_t>(prow[s] * W + i) * 4u : kOut, 0, 0));
+            float, __builtin_amdgcn_raw_buffer_load_b32(rsrc, ok ? (rb + static_cast<uint32_t>(i)) * 4u : kOut, 0, 0));
       }
       advance(prow[s], pcol[s]);
     }
   };
 #pragma unroll
   for (int u = 0; u < PF; ++u) load_phase(pf[u]);
+  __syncthreads();  // ring cleared
 
   for (int p0 = 0; p0 < a.phases; p0 += PF) {
 #pragma unroll
@@ -122,37 +127,31 @@ __global__ __launch_bounds__(kDitherMaxThreads) void dither_kernel(DitherArgs a)
         const int j = row[s], i0 = col[s];
         // row above, columns i0-1 .. i0+K (written in earlier phases)
         const float* up = ering + ((j - 1) & rmask) * D;
+        float* me = ering + (j & rmask) * D;
         float ua[K + 2];
 #pragma unroll
         for (int c = 0; c < K + 2; ++c) ua[c] = up[(i0 - 1 + c) & (D - 1)];
-        const bool has_up = j > 0 && j < H;
+        const bool live_row = j < H;
+        const bool starts = i0 < 0 && i0 + K >= 0;  // this phase holds column -1
+        const uint32_t rb = static_cast<uint32_t>(j) * static_cast<uint32_t>(W);
 #pragma unroll
         for (int c = 0; c < K; ++c) {
           const int i = i0 + c;
-          const bool act = i >= 0 && i < W && j < H;
-          const float q = (nsamp * pf[u][s][c]) / total;
-          const float I = clamp ? (tpos ? fminf(1.f, q) : 0.f) : q;
-          const float p1 = w1 * ua[c], p5 = w5 * ua[c + 1], p3 = w3 * ua[c + 2], p7 = w7 * eleft[s];
-          float err = 0.f;
-          const float e1 = err + p1;
-          err = (has_up && i >= 1) ? e1 : err;
-          const float e5 = err + p5;
-          err = has_up ? e5 : err;
-          const float e3 = err + p3;
-          err = (has_up && i + 1 < W) ? e3 : err;
-          const float e7 = err + p7;
-          err = i >= 1 ? e7 : err;
-          const float v = I + err;
+          const bool act = live_row && i >= 0 && i < W;
+          // arrival order: below-right push of (i-1, j-1), below of (i, j-1),
+          // below-left of (i+1, j-1), right of (i-1, j).  The oracle starts
+          // from +0; starting from the first product differs only in the sign
+          // of a zero sum.
+          const float err = ((w1 * ua[c] + w5 * ua[c + 1]) + w3 * ua[c + 2]) + w7 * eleft[s];
+          const float v = pf[u][s][c] + err;
           const bool sel = v >= 0.5f;
-          const float e = v - (sel ? 1.f : 0.f);
+          const float e = act ? v - (sel ? 1.f : 0.f) : 0.f;
           eleft[s] = e;
-          // only cells of the image write: a ring row's entries may still be
-          // read for the row it held before, until its new row starts
-          if (act) ering[(j & rmask) * D + (i & (D - 1))] = e;
+          if (live_row && (act || i == W || (starts && i < 0))) me[i & (D - 1)] = e;
           __builtin_amdgcn_raw_buffer_store_b8(static_cast<uint8_t>(sel ? 1 : 0), rmask_out,
-                                               act ? static_cast<uint32_t>(j * W + i) : kOut, 0, 0);
+                                               act ? rb + static_cast<uint32_t>(i) : kOut, 0, 0);
         }
-        advance(row[s], col[s]);
+        if (advance(row[s], col[s])) eleft[s] = 0.f;
       }
       // loads for PF phases ahead reuse this phase's registers
       load_phase(pf[u]);
@@ -163,37 +162,82 @@ __global__ __launch_bounds__(kDitherMaxThreads) void dither_kernel(DitherArgs a)
   }
 }
 
-// Belief map of the stored belief and its FP64 sum (rounded to FP32).
-template <typename T>
-__device__ inline float to_f32(T v) {
-  return static_cast<float>(v);
-}
-template <>
-__device__ inline float to_f32<__bf16>(__bf16 v) {
-  return __uint_as_float(static_cast<uint32_t>(__builtin_bit_cast(uint16_t, v)) << 16);
+// I = min(1, n m / total) in place (FP32 product and quotient rounded to
+// nearest; a total that is not positive gives I = 0).
+__global__ void intensity_kernel(float* __restrict__ m, uint32_t cells, float n, const FilterDev* __restrict__ dev) {
+  const float total = dev->dither_total;
+  const bool tpos = total > 0.f;
+  for (uint32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < cells; e += gridDim.x * blockDim.x)
+    m[e] = tpos ? fminf(1.f, (n * m[e]) / total) : 0.f;
 }
 
+// Belief map of the stored belief and its FP64 sum (rounded to FP32).
+// A thread takes a run of four cells of a row (the pitch is a multiple of
+// eight) and reads the run's heading planes kSrcBatch at a time, the loads
+// of a batch all in flight.
 constexpr int kSrcThreads = 256;
 constexpr int kSrcMaxBlocks = 1024;
+constexpr int kSrcBatch = 24;
+
+template <typename T>
+__device__ inline void load_run(const T* p, float v[4]);
+template <>
+__device__ inline void load_run<float>(const float* p, float v[4]) {
+  const float4 q = *reinterpret_cast<const float4*>(p);
+  v[0] = q.x;
+  v[1] = q.y;
+  v[2] = q.z;
+  v[3] = q.w;
+}
+template <>
+__device__ inline void load_run<__bf16>(const __bf16* p, float v[4]) {
+  const uint2 q = *reinterpret_cast<const uint2*>(p);
+  v[0] = __uint_as_float(q.x << 16);
+  v[1] = __uint_as_float(q.x & 0xffff0000u);
+  v[2] = __uint_as_float(q.y << 16);
+  v[3] = __uint_as_float(q.y & 0xffff0000u);
+}
+template <>
+__device__ inline void load_run<_Float16>(const _Float16* p, float v[4]) {
+  typedef __attribute__((__vector_size__(4 * sizeof(_Float16)))) _Float16 h4;
+  const h4 q = *reinterpret_cast<const h4*>(p);
+  for (int i = 0; i < 4; ++i) v[i] = static_cast<float>(q[i]);
+}
 
 template <typename T>
 __global__ __launch_bounds__(kSrcThreads) void dither_source_kernel(const void* buf0, const void* buf1, int W,
                                                                    int pitch, int n_theta, int64_t sstride,
-                                                                   uint32_t cells, double* partials,
-                                                                   FilterDev* dev, float* out) {
+                                                                   int runs, double* partials, FilterDev* dev,
+                                                                   float* out) {
   __shared__ double rs[kSrcThreads];
   __shared__ int last_flag;
   const int t = threadIdx.x;
   const T* bel = static_cast<const T*>(dev->cur ? buf1 : buf0);
+  const int rpr = pitch / 4;  // runs per row
   double s = 0.0;
-  for (uint32_t e = blockIdx.x * kSrcThreads + t; e < cells; e += gridDim.x * kSrcThreads) {
-    const uint32_t j = e / static_cast<uint32_t>(W), i = e - j * static_cast<uint32_t>(W);
-    const T* p = bel + static_cast<int64_t>(j) * pitch + i;
-    float m = 0.f;
-#pragma unroll 8
-    for (int k = 0; k < n_theta; ++k) m = fmaxf(m, to_f32<T>(p[k * sstride]));
-    out[e] = m;
-    s += static_cast<double>(m);
+  for (int q = blockIdx.x * kSrcThreads + t; q < runs; q += gridDim.x * kSrcThreads) {
+    const int j = q / rpr, i0 = 4 * (q - j * rpr);
+    const T* p = bel + static_cast<int64_t>(j) * pitch + i0;
+    float m[4] = {0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < n_theta; k0 += kSrcBatch) {
+      float v[kSrcBatch][4];
+#pragma unroll
+      for (int b = 0; b < kSrcBatch; ++b) {
+        const int k = min(k0 + b, n_theta - 1);  // repeats of the last plane leave the max unchanged
+        load_run<T>(p + k * sstride, v[b]);
+      }
+#pragma unroll
+      for (int b = 0; b < kSrcBatch; ++b)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) m[c] = fmaxf(m[c], v[b][c]);
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      if (i0 + c < W) {
+        out[static_cast<int64_t>(j) * W + i0 + c] = m[c];
+        s += static_cast<double>(m[c]);
+      }
+    }
   }
   rs[t] = s;
   __syncthreads();
@@ -202,9 +246,8 @@ __global__ __launch_bounds__(kSrcThreads) void dither_source_kernel(const void* 
     __syncthreads();
   }
   if (t == 0) {
-    partials[blockIdx.x] = rs[0];
-    const uint32_t prev = __hip_atomic_fetch_add(&dev->counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    last_flag = (prev == gridDim.x - 1);
+    publish(&partials[blockIdx.x], rs[0]);
+    last_flag = arrive_last(dev, blockIdx.x, gridDim.x);
   }
   __syncthreads();
   if (!last_flag) return;
@@ -239,12 +282,17 @@ int next_pow2(int x) {
 DitherPlan plan_for(int W, int H, int K) {
   DitherPlan p;
   p.K = K;
-  // rows that are active at once (a slot moves to its next row (K+1) span columns back)
-  const int64_t need = std::min<int64_t>(H, (static_cast<int64_t>(W) + K - 1 + K) / (K + 1));
+  // rows in flight at once: a slot takes its next row (K+1) span columns
+  // back, once its current row is past column W
+  const int64_t need = std::min<int64_t>(H, (static_cast<int64_t>(W) + K + K) / (K + 1));
   const int64_t nt = std::min<int64_t>(kDitherMaxThreads, (need + 63) / 64 * 64);
   const int64_t slots = (need + nt - 1) / nt;
-  // ring rows: a row's entries are reused by row j + ring only after row j + 1 is done
-  const int64_t rows = std::min<int64_t>(H, 1 + (static_cast<int64_t>(W) + K - 1 + K) / (K + 1));
+  // ring rows: row j + ring first writes (its column -1, at step
+  // (K+1)(j+ring) - 1) in a later phase than row j + 1 last reads row j
+  // (step (K+1)(j+1) + W - 1); without reuse one more row, so that row -1
+  // reads a ring row that stays zero
+  const int64_t rows = std::min<int64_t>(static_cast<int64_t>(H) + 1,
+                                         1 + (static_cast<int64_t>(W) + K + K) / (K + 1));
   if (slots > kDitherMaxSlots || rows > (1 << 20)) return p;
   p.ring = next_pow2(static_cast<int>(rows));
   p.lds = static_cast<size_t>(p.ring) * ring_cols(K) * sizeof(float);
@@ -266,7 +314,8 @@ template <int K, int MAXA>
 hipError_t launch_k(const DitherArgs& a0, const DitherPlan& p, hipStream_t s) {
   constexpr int PF = K == 1 ? 16 : 4;
   DitherArgs a = a0;
-  const int64_t last = static_cast<int64_t>(a.W - 1) + static_cast<int64_t>(K + 1) * (a.H - 1);
+  // the last visit is the zero write at column W of the last row
+  const int64_t last = static_cast<int64_t>(a.W) + static_cast<int64_t>(K + 1) * (a.H - 1);
   const int64_t phases = last / K + 1;
   a.phases = static_cast<int32_t>((phases + PF - 1) / PF * PF);
   hipLaunchKernelGGL((dither_kernel<K, MAXA, PF>), dim3(1), dim3(p.threads), p.lds, s, a);
@@ -289,36 +338,33 @@ hipError_t launch_dither(const float* src, int W, int H, uint8_t* mask, bool sca
   DitherArgs a = {};
   a.src = src;
   a.mask = mask;
-  a.dev = dev;
   a.W = W;
   a.H = H;
   a.ring = p.ring;
-  a.scaled = scaled ? 1 : 0;
-  a.n = n_samples;
   a.cells = static_cast<uint32_t>(static_cast<int64_t>(W) * H);
+  if (scaled) {
+    // the belief map in src becomes the intensity, in place
+    const int blocks = static_cast<int>(std::min<int64_t>(1024, (a.cells + 255) / 256));
+    hipLaunchKernelGGL(intensity_kernel, dim3(blocks), dim3(256), 0, s, const_cast<float*>(src), a.cells, n_samples, dev);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
   if (p.K == 3) {
-    switch (p.slots) {
-      case 1: return launch_k<3, 1>(a, p, s);
-      case 2: return launch_k<3, 2>(a, p, s);
-      default: return launch_k<3, 4>(a, p, s);
-    }
+    if (p.slots == 1) return launch_k<3, 1>(a, p, s);
+    return launch_k<3, 2>(a, p, s);
   }
-  switch (p.slots) {
-    case 1: return launch_k<1, 1>(a, p, s);
-    case 2: return launch_k<1, 2>(a, p, s);
-    default: return launch_k<1, 4>(a, p, s);
-  }
+  return launch_k<1, 4>(a, p, s);
 }
 
 hipError_t launch_dither_source(int dtype, const void* buf0, const void* buf1, int W, int H, int pitch,
                                 int n_theta, int64_t sstride, double* partials, FilterDev* dev, float* out,
                                 hipStream_t s) {
-  const uint32_t cells = static_cast<uint32_t>(static_cast<int64_t>(W) * H);
-  const int blocks = static_cast<int>(std::min<int64_t>(kSrcMaxBlocks, (cells + kSrcThreads - 1) / kSrcThreads));
+  const int runs = static_cast<int>(static_cast<int64_t>(H) * pitch / 4);
+  const int blocks = std::max(1, std::min(kSrcMaxBlocks, (runs + kSrcThreads - 1) / kSrcThreads));
   switch (dtype) {
-    case 0: hipLaunchKernelGGL(dither_source_kernel<float>, dim3(blocks), dim3(kSrcThreads), 0, s, buf0, buf1, W, pitch, n_theta, sstride, cells, partials, dev, out); break;
-    case 1: hipLaunchKernelGGL(dither_source_kernel<__bf16>, dim3(blocks), dim3(kSrcThreads), 0, s, buf0, buf1, W, pitch, n_theta, sstride, cells, partials, dev, out); break;
-    case 2: hipLaunchKernelGGL(dither_source_kernel<_Float16>, dim3(blocks), dim3(kSrcThreads), 0, s, buf0, buf1, W, pitch, n_theta, sstride, cells, partials, dev, out); break;
+    case 0: hipLaunchKernelGGL(dither_source_kernel<float>, dim3(blocks), dim3(kSrcThreads), 0, s, buf0, buf1, W, pitch, n_theta, sstride, runs, partials, dev, out); break;
+    case 1: hipLaunchKernelGGL(dither_source_kernel<__bf16>, dim3(blocks), dim3(kSrcThreads), 0, s, buf0, buf1, W, pitch, n_theta, sstride, runs, partials, dev, out); break;
+    case 2: hipLaunchKernelGGL(dither_source_kernel<_Float16>, dim3(blocks), dim3(kSrcThreads), 0, s, buf0, buf1, W, pitch, n_theta, sstride, runs, partials, dev, out); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

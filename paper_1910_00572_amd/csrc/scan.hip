@@ -381,7 +381,7 @@ __global__ __launch_bounds__(kScanThreads) void scan_gemm_kernel(ScanArgs a) {
   const float ref_lb = red_lb[0];
   if (t == 0) {
     // L_ref in FP64 from the stored value and the exact integer distance
-    a.partials[blockIdx.x] = has_ref ? static_cast<double>(ref_lb) - static_cast<double>(a.c) * ref_d : -INFINITY;
+    publish(&a.partials[blockIdx.x], has_ref ? static_cast<double>(ref_lb) - static_cast<double>(a.c) * ref_d : -INFINITY);
   }
   // write L - L_ref for every state of the tile (both terms are differences
   // of nearby quantities: no large cancellation)
@@ -406,8 +406,7 @@ __global__ __launch_bounds__(kScanThreads) void scan_gemm_kernel(ScanArgs a) {
   // last workgroup: M* = max over tiles
   __syncthreads();
   if (t == 0) {
-    const uint32_t prev = __hip_atomic_fetch_add(&dev->counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    last_flag = (prev == static_cast<uint32_t>(gridDim.x - 1));
+    last_flag = arrive_last(dev, blockIdx.x, gridDim.x);
   }
   __syncthreads();
   if (!last_flag) return;
@@ -474,10 +473,9 @@ __global__ __launch_bounds__(kScanThreads) void scan_apply_kernel(ScanArgs a) {
     __syncthreads();
   }
   if (t == 0) {
-    part[2 * blk] = rs[0];
-    part[2 * blk + 1] = static_cast<double>(rm[0]);
-    const uint32_t prev = __hip_atomic_fetch_add(&dev->counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    last_flag = (prev == static_cast<uint32_t>(nblk - 1));
+    publish(&part[2 * blk], rs[0]);
+    publish(&part[2 * blk + 1], static_cast<double>(rm[0]));
+    last_flag = arrive_last(dev, static_cast<uint32_t>(blk), static_cast<uint32_t>(nblk));
   }
   __syncthreads();
   if (!last_flag) return;
@@ -528,11 +526,12 @@ __global__ __launch_bounds__(kScanThreads) void scan_apply_kernel(ScanArgs a) {
 //            restricted to the listed rows of the range table (each lane
 //            gathers its own 16-byte operand pieces); D* by a last-workgroup
 //            reduction.  D is stored per (list position, channel).
-//   pass 2   the whole belief is read once for its sum and max; sampled
-//            states are multiplied in place and their old values kept where
-//            D was.  The last workgroup updates the log-normaliser by
-//            ln sum - c D* - ln(previous sum), or, if no mass is left, puts
-//            the old values back and flags the filter degenerate.
+//   pass 2a  sampled states are multiplied in place, their old values kept
+//            where D was
+//   pass 2b  the whole belief is read once for its sum and max; the last
+//            workgroup updates the log-normaliser by ln sum - c D* -
+//            ln(previous sum), or, if no mass is left, puts the old values
+//            back and flags the filter degenerate.
 struct SampledArgs {
   const void* rq;       // MFMA-tiled range table
   const int32_t* sr;    // [cells] sum of squares per cell
@@ -542,7 +541,7 @@ struct SampledArgs {
   int32_t* list;        // [nsel] selected cells (pitch layout)
   int32_t* pos;         // [cells] position in the list, -1 = not selected
   int32_t* dsc;         // [nsel][n_theta] D (pass 1), then the old value as FP32 bits (pass 2)
-  double* partials;     // pass 1: one per workgroup; pass 2: two per workgroup after them
+  double* partials;     // pass 1: one per workgroup; pass 2b: two per workgroup after them
   FilterDev* dev;
   int32_t cells, n_theta, npad, kpad, W, H, pitch;
   int64_t sstride;
@@ -550,40 +549,60 @@ struct SampledArgs {
   float c;              // h^2 / (2 sigma^2), FP32 (factors)
   double c64;           // the same in FP64 (log-normaliser)
   int32_t p1_blocks;    // pass-1 workgroups (offset of the pass-2 partials)
-  int32_t kchunk;       // channels per pass-2 workgroup
   uint32_t rq_bytes;
 };
 
 constexpr int kCompactThreads = 256;
+constexpr int kCompactMaxBlocks = 1024;
 
-__global__ __launch_bounds__(kCompactThreads) void compact_kernel(SampledArgs a) {
-  const int lane = threadIdx.x & 63;
+// One workgroup per stretch of cells, a wave per quarter of it: a counting
+// pass, one atomic per workgroup for the list offset, then the writing pass
+// (the mask bytes come from the caches the second time).
+__global__ __launch_bounds__(kCompactThreads) void compact_kernel(SampledArgs a, int per_wave) {
+  __shared__ int wcount[kCompactThreads / 64];
+  __shared__ int bbase;
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
   const uint32_t n = static_cast<uint32_t>(a.cells);
-  for (uint32_t c0 = blockIdx.x * kCompactThreads; c0 < n; c0 += gridDim.x * kCompactThreads) {
-    const uint32_t cell = c0 + threadIdx.x;
+  const uint32_t w0 = (blockIdx.x * (kCompactThreads / 64) + wv) * static_cast<uint32_t>(per_wave) * 64u;
+  auto selected = [&](uint32_t cell) {
     const uint32_t j = cell / static_cast<uint32_t>(a.pitch), i = cell - j * static_cast<uint32_t>(a.pitch);
-    const bool sel = cell < n && i < static_cast<uint32_t>(a.W) && a.mask[j * static_cast<uint32_t>(a.W) + i] != 0;
+    return cell < n && i < static_cast<uint32_t>(a.W) && a.mask[j * static_cast<uint32_t>(a.W) + i] != 0;
+  };
+  int cnt = 0;
+  for (int it = 0; it < per_wave; ++it) cnt += __popcll(__ballot(selected(w0 + it * 64u + lane)));
+  if (lane == 0) wcount[wv] = cnt;
+  __syncthreads();
+  if (t == 0) {
+    int tot = 0;
+    for (int w = 0; w < kCompactThreads / 64; ++w) tot += wcount[w];
+    bbase = tot > 0 ? __hip_atomic_fetch_add(&a.dev->nsel, tot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0;
+  }
+  __syncthreads();
+  int off = bbase;
+  for (int w = 0; w < wv; ++w) off += wcount[w];
+  const uint64_t below = (1ull << lane) - 1ull;
+  for (int it = 0; it < per_wave; ++it) {
+    const uint32_t cell = w0 + it * 64u + lane;
+    const bool sel = selected(cell);
     const uint64_t bal = __ballot(sel);
-    const int cnt = __popcll(bal);
-    int base = 0;
-    if (cnt > 0 && lane == 0)
-      base = __hip_atomic_fetch_add(&a.dev->nsel, cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    base = __shfl(base, 0);
-    const int idx = base + __popcll(bal & ((1ull << lane) - 1ull));
+    const int idx = off + __popcll(bal & below);
     if (sel) a.list[idx] = static_cast<int32_t>(cell);
     if (cell < n) a.pos[cell] = sel ? idx : -1;
+    off += __popcll(bal);
   }
 }
 
-// Pass 1.  One work item = 32 listed cells x one 32-channel block.
-template <typename OP>
+// Pass 1.  One work item = 32 listed cells x one 32-channel block.  With the
+// depth known at compile time (KPAD > 0) the depth loop is unrolled and its
+// operand loads run PA steps ahead.
+template <typename OP, int KPAD>
 __global__ __launch_bounds__(kScanThreads) void sampled_gemm_kernel(SampledArgs a) {
   __shared__ int red[kScanThreads / 64];
   __shared__ double red_d[kScanThreads];
   __shared__ int last_flag;
   constexpr int KSTEP = Mfma<OP>::KSTEP, HALF = Mfma<OP>::HALF, EB = sizeof(OP);
   using Vec = typename Mfma<OP>::Vec;
-  constexpr int PA = 4;
+  constexpr int PA = 8;
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
   const int half = lane >> 5, col = lane & 31;
   FilterDev* dev = a.dev;
@@ -592,7 +611,7 @@ __global__ __launch_bounds__(kScanThreads) void sampled_gemm_kernel(SampledArgs 
   const int items = (nsel + 31) / 32 * nblocks;
   const int64_t ngroups = (a.cells + 31) / 32;
   const uint32_t astep_bytes = static_cast<uint32_t>(ngroups * 64 * HALF * EB);
-  const int nsteps = a.kpad / KSTEP;  // a multiple of PA
+  const int nsteps = KPAD > 0 ? KPAD / KSTEP : a.kpad / KSTEP;  // a multiple of 4
   const __amdgpu_buffer_rsrc_t ra = __builtin_amdgcn_make_buffer_rsrc(
       const_cast<void*>(a.rq), static_cast<short>(0), static_cast<int>(a.rq_bytes), 0x00020000);
   const __amdgpu_buffer_rsrc_t rb = __builtin_amdgcn_make_buffer_rsrc(
@@ -611,16 +630,32 @@ __global__ __launch_bounds__(kScanThreads) void sampled_gemm_kernel(SampledArgs 
     f32x16 acc;
 #pragma unroll
     for (int i = 0; i < 16; ++i) acc[i] = 0.f;
-    Vec abuf[PA], bbuf[PA];
+    if constexpr (KPAD > 0) {
+      constexpr int KS = KPAD / KSTEP;
+      constexpr int P = PA < KS ? PA : KS;
+      Vec abuf[P], bbuf[P];
 #pragma unroll
-    for (int u = 0; u < PA; ++u) load(u, abuf[u], bbuf[u]);
-    for (int st = 0; st < nsteps; st += PA) {
+      for (int u = 0; u < P; ++u) load(u, abuf[u], bbuf[u]);
 #pragma unroll
-      for (int u = 0; u < PA; ++u) {
-        Mfma<OP>::mma(abuf[u], bbuf[u], acc);
+      for (int st = 0; st < KS; ++st) {
+        Mfma<OP>::mma(abuf[st % P], bbuf[st % P], acc);
         __builtin_amdgcn_sched_barrier(0);
-        load(st + u + PA, abuf[u], bbuf[u]);
+        if (st + P < KS) load(st + P, abuf[st % P], bbuf[st % P]);
         __builtin_amdgcn_sched_barrier(0);
+      }
+    } else {
+      constexpr int P = 4;
+      Vec abuf[P], bbuf[P];
+#pragma unroll
+      for (int u = 0; u < P; ++u) load(u, abuf[u], bbuf[u]);
+      for (int st = 0; st < nsteps; st += P) {
+#pragma unroll
+        for (int u = 0; u < P; ++u) {
+          Mfma<OP>::mma(abuf[u], bbuf[u], acc);
+          __builtin_amdgcn_sched_barrier(0);
+          load(st + u + P, abuf[u], bbuf[u]);
+          __builtin_amdgcn_sched_barrier(0);
+        }
       }
     }
     // rows are list positions, columns channels (accumulator layout of the dense pass)
@@ -648,9 +683,8 @@ __global__ __launch_bounds__(kScanThreads) void sampled_gemm_kernel(SampledArgs 
   if (t == 0) {
     int m = red[0];
     for (int w = 1; w < kScanThreads / 64; ++w) m = min(m, red[w]);
-    a.partials[blockIdx.x] = static_cast<double>(m);
-    const uint32_t prev = __hip_atomic_fetch_add(&dev->counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    last_flag = (prev == gridDim.x - 1);
+    publish(&a.partials[blockIdx.x], static_cast<double>(m));
+    last_flag = arrive_last(dev, blockIdx.x, gridDim.x);
   }
   __syncthreads();
   if (!last_flag) return;
@@ -669,50 +703,63 @@ __global__ __launch_bounds__(kScanThreads) void sampled_gemm_kernel(SampledArgs 
   }
 }
 
-// Pass 2.  Grid (quad blocks, channel chunks): a thread takes runs of four
-// cells and walks the chunk's channels, so the positions are read once per
-// chunk.
+// Pass 2a.  One thread per sampled state (list position r, channel k):
+// multiply the stored value in place by exp(-c (D - D*)) and keep the old
+// value where D was.
+template <typename T>
+__global__ __launch_bounds__(kScanThreads) void sampled_scale_kernel(SampledArgs a) {
+  FilterDev* dev = a.dev;
+  const int dstar = dev->dstar;
+  if (dstar == INT32_MAX) return;  // no sample
+  const int nsel = __hip_atomic_load(&dev->nsel, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  T* bel = static_cast<T*>(a.buf[dev->cur]);
+  float* old = reinterpret_cast<float*>(a.dsc);
+  const int n = nsel * a.n_theta;  // below 2^31: checked on the host
+  for (int e = blockIdx.x * kScanThreads + threadIdx.x; e < n; e += gridDim.x * kScanThreads) {
+    const int r = e / a.n_theta, k = e - r * a.n_theta;
+    T* p = bel + static_cast<int64_t>(k) * a.sstride + a.list[r];
+    const float v = static_cast<float>(*p);
+    const int d = a.dsc[e];
+    old[e] = v;
+    *p = static_cast<T>(v * expf(-a.c * static_cast<float>(d - dstar)));
+  }
+}
+
+// Pass 2b.  Sum and max of the whole stored belief (padding cells hold zero),
+// streamed flat: a thread reads four runs of four values per round, a wave a
+// contiguous stretch.  The last workgroup updates the filter scalars, or
+// puts the old sampled values back if no mass is left.
 template <typename T>
 __global__ __launch_bounds__(kScanThreads) void sampled_apply_kernel(SampledArgs a) {
   __shared__ double rs[kScanThreads];
   __shared__ float rm[kScanThreads];
   __shared__ int last_flag;
+  constexpr int U = 4;
   const int t = threadIdx.x;
+  const int nthr = kScanThreads;
   FilterDev* dev = a.dev;
   const int dstar = dev->dstar;
   if (dstar == INT32_MAX) return;  // no sample: no update (uniform across the grid)
   T* bel = static_cast<T*>(a.buf[dev->cur]);
   float* old = reinterpret_cast<float*>(a.dsc);
-  const int k0 = blockIdx.y * a.kchunk, k1 = min(a.n_theta, k0 + a.kchunk);
-  const int blk = blockIdx.y * gridDim.x + blockIdx.x;
-  const int nblk = gridDim.x * gridDim.y;
+  const int blk = blockIdx.x, nblk = gridDim.x;
   double* part = a.partials + a.p1_blocks;
-  const int nquads = a.cells / 4;
+  const int64_t nruns = a.sstride / 4 * a.n_theta;
   double s = 0.0;
   float mx = 0.f;
-  for (int q = blockIdx.x * kScanThreads + t; q < nquads; q += gridDim.x * kScanThreads) {
-    const int cell = 4 * q;
-    const int4 p4 = *reinterpret_cast<const int4*>(a.pos + cell);
-    const int pr[4] = {p4.x, p4.y, p4.z, p4.w};
-    const bool any = (p4.x & p4.y & p4.z & p4.w) >= 0;  // some position is not -1
-    for (int k = k0; k < k1; ++k) {
-      T* p = bel + static_cast<int64_t>(k) * a.sstride + cell;
-      float v[4];
-      load4<T>(p, v);
-      if (any) {
+  for (int64_t b = static_cast<int64_t>(blockIdx.x) * kScanThreads * U + t; b < nruns;
+       b += static_cast<int64_t>(gridDim.x) * kScanThreads * U) {
+    float v[U][4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          if (pr[u] >= 0) {
-            const int64_t idx = static_cast<int64_t>(pr[u]) * a.n_theta + k;
-            const int d = a.dsc[idx];
-            old[idx] = v[u];
-            v[u] = v[u] * expf(-a.c * static_cast<float>(d - dstar));
-          }
-        }
-        store4<T>(p, v);
-      }
-      s += static_cast<double>((v[0] + v[1]) + (v[2] + v[3]));
-      mx = fmaxf(mx, fmaxf(fmaxf(v[0], v[1]), fmaxf(v[2], v[3])));
+    for (int u = 0; u < U; ++u) {
+      const int64_t i = b + static_cast<int64_t>(u) * kScanThreads;
+      if (i < nruns) load4<T>(bel + 4 * i, v[u]);
+      else v[u][0] = v[u][1] = v[u][2] = v[u][3] = 0.f;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      s += static_cast<double>((v[u][0] + v[u][1]) + (v[u][2] + v[u][3]));
+      mx = fmaxf(mx, fmaxf(fmaxf(v[u][0], v[u][1]), fmaxf(v[u][2], v[u][3])));
     }
   }
   rs[t] = s;
@@ -726,16 +773,15 @@ __global__ __launch_bounds__(kScanThreads) void sampled_apply_kernel(SampledArgs
     __syncthreads();
   }
   if (t == 0) {
-    part[2 * blk] = rs[0];
-    part[2 * blk + 1] = static_cast<double>(rm[0]);
-    const uint32_t prev = __hip_atomic_fetch_add(&dev->counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    last_flag = (prev == static_cast<uint32_t>(nblk - 1));
+    publish(&part[2 * blk], rs[0]);
+    publish(&part[2 * blk + 1], static_cast<double>(rm[0]));
+    last_flag = arrive_last(dev, static_cast<uint32_t>(blk), static_cast<uint32_t>(nblk));
   }
   __syncthreads();
   if (!last_flag) return;
   double ts = 0.0;
   float tm = 0.f;
-  for (int b = t; b < nblk; b += kScanThreads) {
+  for (int b = t; b < nblk; b += nthr) {
     ts += __hip_atomic_load(&part[2 * b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     tm = fmaxf(tm, static_cast<float>(__hip_atomic_load(&part[2 * b + 1], __ATOMIC_RELAXED,
                                                         __HIP_MEMORY_SCOPE_AGENT)));
@@ -757,7 +803,7 @@ __global__ __launch_bounds__(kScanThreads) void sampled_apply_kernel(SampledArgs
   if (degenerate) {
     // every sampled state went to zero and nothing else holds mass: restore
     const int64_t n = static_cast<int64_t>(nsel) * a.n_theta;
-    for (int64_t e = t; e < n; e += kScanThreads) {
+    for (int64_t e = t; e < n; e += nthr) {
       const int r = static_cast<int>(e / a.n_theta), k = static_cast<int>(e - static_cast<int64_t>(r) * a.n_theta);
       bel[static_cast<int64_t>(k) * a.sstride + a.list[r]] = static_cast<T>(old[e]);
     }
@@ -1013,24 +1059,40 @@ hipError_t scan_sampled_launch(const ScanLaunch& L, const float* ranges_m, doubl
   a.c64 = h * h / (2.0 * sigma_m * sigma_m);
   a.c = static_cast<float>(a.c64);
   a.rq_bytes = static_cast<uint32_t>(t.rq_bytes);
-  a.kchunk = 8;
-  const int g0 = std::min(1024, (a.cells + kCompactThreads - 1) / kCompactThreads);
-  hipLaunchKernelGGL(compact_kernel, dim3(g0), dim3(kCompactThreads), 0, L.stream, a);
+  // compaction: at most kCompactMaxBlocks workgroups, at least four rounds of 64 cells per wave
+  const int64_t waves_needed = (static_cast<int64_t>(a.cells) + 255) / 256;
+  const int64_t g0 = std::min<int64_t>(kCompactMaxBlocks, (waves_needed + 3) / 4);
+  const int per_wave = static_cast<int>((a.cells + g0 * 4 * 64 - 1) / (g0 * 4 * 64));
+  hipLaunchKernelGGL(compact_kernel, dim3(static_cast<int>(g0)), dim3(kCompactThreads), 0, L.stream, a, per_wave);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   a.p1_blocks = std::min(256, std::max(1, (a.cells + 127) / 128));
-  if (t.f32)
-    hipLaunchKernelGGL(sampled_gemm_kernel<float>, dim3(a.p1_blocks), dim3(kScanThreads), 0, L.stream, a);
-  else
-    hipLaunchKernelGGL(sampled_gemm_kernel<__bf16>, dim3(a.p1_blocks), dim3(kScanThreads), 0, L.stream, a);
+  const dim3 g1(a.p1_blocks), b1(kScanThreads);
+  if (t.f32) {
+    if (t.kpad == 384) hipLaunchKernelGGL((sampled_gemm_kernel<float, 384>), g1, b1, 0, L.stream, a);
+    else hipLaunchKernelGGL((sampled_gemm_kernel<float, 0>), g1, b1, 0, L.stream, a);
+  } else {
+    if (t.kpad == 384) hipLaunchKernelGGL((sampled_gemm_kernel<__bf16, 384>), g1, b1, 0, L.stream, a);
+    else hipLaunchKernelGGL((sampled_gemm_kernel<__bf16, 0>), g1, b1, 0, L.stream, a);
+  }
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  const int ky = (L.n_theta + a.kchunk - 1) / a.kchunk;
-  const int nq = a.cells / 4;
-  const int qx = std::max(1, std::min((nq + kScanThreads - 1) / kScanThreads, kScanApplyBlocks / ky));
-  const dim3 g2(qx, ky);
+  // pass 2: scale the sampled states, then the sum/max stream
+  if (static_cast<int64_t>(a.cells) * L.n_theta >= (static_cast<int64_t>(1) << 31)) return hipErrorInvalidValue;
+  const int g2a = std::max(1, std::min(1024, (a.cells / 8 * L.n_theta + kScanThreads - 1) / kScanThreads));
+  const int64_t runs = L.sstride / 4 * L.n_theta;
+  const int g2b = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(2048, (runs + 4 * kScanThreads - 1) / (4 * kScanThreads))));
   switch (L.dtype) {
-    case 0: hipLaunchKernelGGL(sampled_apply_kernel<float>, g2, dim3(kScanThreads), 0, L.stream, a); break;
-    case 1: hipLaunchKernelGGL(sampled_apply_kernel<__bf16>, g2, dim3(kScanThreads), 0, L.stream, a); break;
-    case 2: hipLaunchKernelGGL(sampled_apply_kernel<_Float16>, g2, dim3(kScanThreads), 0, L.stream, a); break;
+    case 0:
+      hipLaunchKernelGGL(sampled_scale_kernel<float>, dim3(g2a), dim3(kScanThreads), 0, L.stream, a);
+      hipLaunchKernelGGL(sampled_apply_kernel<float>, dim3(g2b), dim3(kScanThreads), 0, L.stream, a);
+      break;
+    case 1:
+      hipLaunchKernelGGL(sampled_scale_kernel<__bf16>, dim3(g2a), dim3(kScanThreads), 0, L.stream, a);
+      hipLaunchKernelGGL(sampled_apply_kernel<__bf16>, dim3(g2b), dim3(kScanThreads), 0, L.stream, a);
+      break;
+    case 2:
+      hipLaunchKernelGGL(sampled_scale_kernel<_Float16>, dim3(g2a), dim3(kScanThreads), 0, L.stream, a);
+      hipLaunchKernelGGL(sampled_apply_kernel<_Float16>, dim3(g2b), dim3(kScanThreads), 0, L.stream, a);
+      break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -27,7 +27,7 @@ struct ScanWork {
 };
 
 // Partials the scan needs: one per 128-cell tile of pass 1, two per pass-2 block
-// (the sampled update needs at most 256 + 2 * 1024).
+// (the sampled update needs at most 256 + 2 * 2048).
 inline int kScanMaxBlocks(int W, int H, int pitch) {
   (void)W;
   return static_cast<int>((static_cast<int64_t>(H) * pitch + 127) / 128) + 2048;

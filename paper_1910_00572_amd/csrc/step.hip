@@ -451,10 +451,9 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int blk, cons
     __syncthreads();
   }
   if (t == 0) {
-    a.partials[2 * blk] = red_s[0];
-    a.partials[2 * blk + 1] = static_cast<double>(red_m[0]);
-    const uint32_t prev = __hip_atomic_fetch_add(&dev->counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    last_flag = (prev == static_cast<uint32_t>(nblk - 1));
+    publish(&a.partials[2 * blk], red_s[0]);
+    publish(&a.partials[2 * blk + 1], static_cast<double>(red_m[0]));
+    last_flag = arrive_last(dev, static_cast<uint32_t>(blk), static_cast<uint32_t>(nblk));
   }
   __syncthreads();
   if (!last_flag) return;
@@ -804,10 +803,9 @@ __device__ __forceinline__ void stream_body(const StepArgs& a, const int blk, co
     __syncthreads();
   }
   if (t == 0) {
-    a.partials[2 * blk] = red_s[0];
-    a.partials[2 * blk + 1] = static_cast<double>(red_m[0]);
-    const uint32_t prev = __hip_atomic_fetch_add(&dev->counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    last_flag = (prev == static_cast<uint32_t>(nblk - 1));
+    publish(&a.partials[2 * blk], red_s[0]);
+    publish(&a.partials[2 * blk + 1], static_cast<double>(red_m[0]));
+    last_flag = arrive_last(dev, static_cast<uint32_t>(blk), static_cast<uint32_t>(nblk));
   }
   __syncthreads();
   if (!last_flag) return;

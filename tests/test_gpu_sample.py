@@ -105,7 +105,7 @@ def test_dither_sizes_and_errors():
     assert lib.mcl_dither(c_void_p(dummy.data_ptr()), -1, 5, c_void_p(m.data_ptr()), s) == mcl.EINVAL
     assert lib.mcl_dither(None, 4, 4, c_void_p(m.data_ptr()), s) == mcl.EINVAL
     assert lib.mcl_dither(c_void_p(dummy.data_ptr()), 4, 4, None, s) == mcl.EINVAL
-    # min(H, W / 2 + 1) above 4096: the error ring would not fit (checked before any launch)
+    # H >= 4096 and W >= 8190: the error ring would not fit (checked before any launch)
     assert lib.mcl_dither(c_void_p(dummy.data_ptr()), 10000, 5000, c_void_p(m.data_ptr()), s) == mcl.EINVAL
     torch.cuda.synchronize()
 
