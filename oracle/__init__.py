@@ -20,6 +20,7 @@ from .filter import (
     wall_weights,
     init_uniform,
     slice_displacements,
+    integer_shifts,
     shift_bilinear,
     blur_x,
     blur_y,
@@ -42,6 +43,7 @@ __all__ = [
     "wall_weights",
     "init_uniform",
     "slice_displacements",
+    "integer_shifts",
     "shift_bilinear",
     "blur_x",
     "blur_y",

@@ -20,6 +20,9 @@ the kernel separates), sampled taps normalised to sum one with radius
 ceil(3 sigma), bilinear warp with zero outside the grid, the pre-step heading
 rotating (u, v), renormalisation after every step with the log of the kept
 mass accumulated, and the sub-cell gate as an option that accumulates motion.
+The integer-shift option reads the warp of Alg. 1 as a whole-cell translation:
+each channel moves by its displacement plus the remainder it carries, rounded
+to whole cells (half up), and carries the new remainder.
 """
 
 from __future__ import annotations
@@ -41,6 +44,7 @@ class OracleParams:
     mask_before_blur: bool = True   # Alg. 1, statement after the warp
     wall_normalize: bool = True     # Alg. 1, division by the kernel activation
     subcell_gate: bool = False      # Alg. 1, "IF |u_{t,k}| >= 1"
+    integer_shift: bool = False     # whole-cell warp with a per-channel remainder carry
 
     def rxy(self) -> int:
         return default_radius(self.sigma_xy) if self.radius_xy < 0 else self.radius_xy
@@ -57,9 +61,10 @@ class FilterState:
     steps: int = 0
     acc: tuple = (0.0, 0.0)    # accumulated world displacement (sub-cell gate only)
     degenerate: bool = False
+    rem: np.ndarray | None = None  # (Theta, 2) carried remainder in cells (integer shift only)
 
     def copy(self) -> "FilterState":
-        return dataclasses.replace(self, B=self.B.copy())
+        return dataclasses.replace(self, B=self.B.copy(), rem=None if self.rem is None else self.rem.copy())
 
 
 # --------------------------------------------------------------------------
@@ -211,6 +216,20 @@ def shift_bilinear(b: np.ndarray, dx: float, dy: float) -> np.ndarray:
     return out
 
 
+def integer_shifts(dx, dy, rem):
+    """Whole-cell displacements with a carried remainder (integer-shift option).
+
+    Channel k moves by n = floor(d + 1/2) cells, d = its displacement plus the
+    remainder it carries, and keeps d - n (so |remainder| <= 1/2 and the sum of
+    the whole-cell moves tracks the summed displacement).  Returns (nx, ny,
+    new remainder).
+    """
+    r = np.zeros((len(dx), 2)) if rem is None else rem
+    d = np.stack([np.asarray(dx, float) + r[:, 0], np.asarray(dy, float) + r[:, 1]], axis=1)
+    n = np.floor(d + 0.5)
+    return n[:, 0], n[:, 1], d - n
+
+
 def step(state: FilterState, occupancy: np.ndarray, p: OracleParams, u: float, v: float,
          w: float, *, M=None, Wt=None) -> FilterState:
     """One odometry step, Alg. 1 followed by renormalisation.
@@ -241,6 +260,8 @@ def step(state: FilterState, occupancy: np.ndarray, p: OracleParams, u: float, v
     else:
         dx, dy = slice_displacements(u, v, state.theta, p.n_theta, p.cell_m)
         ns.theta = state.theta + w
+    if p.integer_shift:
+        dx, dy, ns.rem = integer_shifts(dx, dy, state.rem)
     S = np.empty_like(state.B)
     for k in range(p.n_theta):
         S[k] = shift_bilinear(state.B[k], dx[k], dy[k])
