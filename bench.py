@@ -240,6 +240,43 @@ def bench_sampled(n_scans, n_samples=4096):
     return out
 
 
+def bench_integer_gate(n_steps=200, split=4):
+    """512x512x72 FP32: bilinear warp on every step against the whole-cell warp with carry, with and
+    without the sub-cell gate, on the headline trajectory at a `split`-times higher odometry rate."""
+    import torch
+    from gen import rooms_and_corridors, smooth_trajectory
+    from paper_1910_00572_amd import mcl
+    occ = rooms_and_corridors(512, 512, seed=3)
+    _, odo = smooth_trajectory(occ, 0.05, n_steps, seed=4)
+    sub = np.repeat(np.asarray(odo[:n_steps], dtype=np.float64) / split, split, axis=0)
+    variants = {"bilinear_every_step": mcl.DEFAULT_FLAGS,
+                "whole_cell_carry": mcl.DEFAULT_FLAGS | mcl.INTEGER_SHIFT,
+                "gate_whole_cell_carry": mcl.DEFAULT_FLAGS | mcl.INTEGER_SHIFT | mcl.SUBCELL_GATE}
+    out, beliefs = {}, {}
+    states = occ.size * 72
+    for name, flags in variants.items():
+        m = mcl.Map(occ, 0.05, 1.0, flags=flags)
+        f = mcl.Filter(m, 72, 1.0, storage="f32")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for u, v, w in sub:
+            f.step_odometry(u, v, w)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        b, pose, _, _ = f.read_belief()
+        beliefs[name] = (b.astype(np.float64), pose)
+        out[name] = {"odometry_steps": len(sub), "states_odometry_steps_per_s": states * len(sub) / dt,
+                     "ms_per_odometry_step": dt * 1e3 / len(sub)}
+        del f, m
+        torch.cuda.empty_cache()
+    ref, rpose = beliefs["bilinear_every_step"]
+    for name in ("whole_cell_carry", "gate_whole_cell_carry"):
+        b, pose = beliefs[name]
+        out[name]["l1_vs_bilinear"] = float(np.abs(b - ref).sum())
+        out[name]["argmax_distance_m_vs_bilinear"] = 0.05 * float(np.hypot(pose.i - rpose.i, pose.j - rpose.j))
+    return out
+
+
 def bench_serving(n_requests, seed=8, capacity=None):
     """Poisson stream of mixed filters (grid 128..1024, 36/72 bins, FP32/BF16, scans on half).
 
@@ -298,7 +335,7 @@ def main():
                     help="also run a plain device copy of this many MiB (counter calibration)")
     ap.add_argument("--serving-requests", type=int, default=256)
     ap.add_argument("--only", default="", help="comma-separated extra sections to run "
-                    "(mixed, scan, sampled, serving); default all")
+                    "(mixed, scan, sampled, gate, serving); default all")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: the filter step is a single-GPU kernel and this build "
@@ -363,7 +400,7 @@ def main():
     del f, m
     torch.cuda.empty_cache()
     if not args.no_extra:
-        only = set(x for x in args.only.split(",") if x) or {"mixed", "scan", "sampled", "serving"}
+        only = set(x for x in args.only.split(",") if x) or {"mixed", "scan", "sampled", "gate", "serving"}
         if "mixed" in only:
             log("[bench] 1024x1024x128 FP32 vs BF16")
             out["mixed_precision_1024x1024x128"] = bench_mixed_precision(100)
@@ -373,6 +410,9 @@ def main():
         if "sampled" in only:
             log("[bench] sampled update 512x512x72, 360 beams, 4096 samples")
             out["sampled_scan_512x512x72_360beams"] = bench_sampled(20)
+        if "gate" in only:
+            log("[bench] whole-cell warp and sub-cell gate against bilinear, 512x512x72")
+            out["whole_cell_warp_512x512x72"] = bench_integer_gate()
         if "serving" in only and args.serving_requests > 0:
             log(f"[bench] serving {args.serving_requests} requests")
             out["serving"] = bench_serving(args.serving_requests, capacity=value)

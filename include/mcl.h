@@ -54,7 +54,11 @@ enum {
   MCL_MASK_BEFORE_BLUR = 1u, /* multiply by the traversability map after the warp */
   MCL_WALL_NORMALIZE = 2u,   /* divide by the kernel activation G(B_0) after the blur */
   MCL_SUBCELL_GATE = 4u,     /* accumulate motion until it reaches one cell (Alg. 1 IF) */
-  MCL_SCAN_F32 = 8u          /* scan cross term on FP32 operands instead of BF16 */
+  MCL_SCAN_F32 = 8u,         /* scan cross term on FP32 operands instead of BF16 */
+  MCL_INTEGER_SHIFT = 16u    /* warp by whole cells: each channel moves by its displacement plus the
+                                remainder it carries, rounded half up (floor(d + 1/2)), and carries
+                                d - floor(d + 1/2) to the next warp; with MCL_SUBCELL_GATE the warp
+                                happens when the gate fires */
 };
 
 typedef struct {
@@ -150,7 +154,9 @@ void mcl_filter_destroy(mcl_filter f);
  * (x, y zero-padded, theta circular; Sec. III-A-2), multiplied by
  * M / G(B_0), and renormalised; then theta_offset += w.  With
  * MCL_SUBCELL_GATE the motion is accumulated and applied once it reaches one
- * cell.  EINVAL for non-finite input or |(u, v)| above 1e6 cells. */
+ * cell.  With MCL_INTEGER_SHIFT the warp is a whole-cell translation with a
+ * per-channel remainder carry (the remainders are host state of the handle).
+ * EINVAL for non-finite input or |(u, v)| above 1e6 cells. */
 mcl_status mcl_step_odometry(mcl_filter f, double u_m, double v_m, double w_rad);
 
 /* apply_scan (async): dense observation update (eq. sensor update) with a

@@ -66,7 +66,7 @@ mcl_status check_params(const mcl_params* p, bool need_theta) {
     return fail(MCL_EINVAL, "sigma_xy_cells must be finite and >= 0");
   const int rxy = resolve_radius(p->sigma_xy_cells, p->radius_xy);
   if (rxy > kMaxRadius) return fail(MCL_EINVAL, "xy blur radius %d exceeds %d", rxy, kMaxRadius);
-  if (p->flags & ~0xFu) return fail(MCL_EINVAL, "unknown flags 0x%x", p->flags);
+  if (p->flags & ~0x1Fu) return fail(MCL_EINVAL, "unknown flags 0x%x", p->flags);
   if (need_theta) {
     if (p->n_theta < 1 || p->n_theta > kMaxTheta)
       return fail(MCL_EINVAL, "n_theta must be in [1, %d]", kMaxTheta);
@@ -145,6 +145,8 @@ struct mcl_filter_s {
   int64_t sstride = 0;
   double theta = 0.0;
   double acc_x = 0.0, acc_y = 0.0;
+  double rem[kMaxTheta][2] = {};  // carried remainders of the whole-cell warp, cells
+  int32_t* ishift = nullptr;      // device: whole-cell shifts of the current warp
   int64_t steps = 0;
   StepShape shape;
   float gxy[kMaxTaps] = {};
@@ -164,11 +166,12 @@ bool stream_plane_ok(int W, int H, size_t eb) {
 
 // Launch shape of the step kernel, from measurements on MI355X.  Maps of
 // fewer than 512 64 x 16 tiles: streaming kernel, 8-row strips, 4 waves,
-// two slice buffers (512^2 x 72 FP32: 69 us against 87 for the tiled
-// kernel).  Larger maps: FP32 storage uses the tiled kernel (64 x 16 tiles,
-// 256 threads; 1024^2 x 128: 390 us against 413 for the best streaming
-// shape); 16-bit storage uses the streaming kernel with 16-row strips and
-// 8 waves (1024^2 x 128 BF16: 342 us against 367 tiled).
+// two slice buffers (512^2 x 72 FP32: 57.7 us; 16-row strips 68.5 us, two
+// theta chunks 61.9 us, the tiled kernel 78.7 us).  Larger maps: streaming
+// kernel with 16-row strips, 8 waves and one slice buffer (1024^2 x 128:
+// FP32 332 us against 362 us tiled; BF16 278 us against 306-384 us for the
+// other streaming shapes).  The tiled kernel remains for planes of 1 GiB or
+// more, which the streaming kernel's 32-bit offsets cannot address.
 // MCL_STEP_SHAPE="tx,ty,nt[,chunks[,nbuf]]" overrides the choice (tx = 0:
 // streaming with nbuf source-slice buffers; chunks = 0: automatic).
 StepShape choose_shape(int W, int H, int T, int R, size_t eb) {
@@ -181,7 +184,7 @@ StepShape choose_shape(int W, int H, int T, int R, size_t eb) {
       sh[1] = 8;
       sh[2] = 256;
       sh[3] = 1;
-    } else if (eb == 2) {
+    } else {
       sh[0] = 0;
       sh[1] = 16;
       sh[2] = 512;
@@ -283,6 +286,7 @@ size_t carve_filter(mcl_filter f, void* ws, const mcl_map m, const mcl_params* p
   const int np = std::max(sh.blocks(), std::max(kReduceBlocks, kScanMaxBlocks(m->W, m->H, m->pitch)));
   double* partials = static_cast<double*>(c.take(static_cast<size_t>(np) * 3 * sizeof(double)));
   FilterDev* dev = static_cast<FilterDev*>(c.take(kDevRegionBytes));
+  int32_t* ishift = static_cast<int32_t*>(c.take(2 * kMaxTheta * sizeof(int32_t)));
   float* scratch = nullptr;
   int32_t* samp = nullptr;
   if (m->scan.n_dirs > 0) {
@@ -299,6 +303,7 @@ size_t carve_filter(mcl_filter f, void* ws, const mcl_map m, const mcl_params* p
     f->dev = dev;
     f->scan_scratch = scratch;
     f->samp_list = samp;
+    f->ishift = ishift;
     f->scanw = scan_work_carve(scanw, p->n_theta, m->scan.kpad);
     f->sstride = sstride;
     f->shape = sh;
@@ -468,34 +473,72 @@ mcl_status mcl_init_belief(mcl_map map, const mcl_params* p, void* ws, size_t ws
 
 void mcl_filter_destroy(mcl_filter f) { delete f; }
 
+// Host bookkeeping of one odometry step (Sec. III-A-1, Alg. 1): the heading
+// offset, the sub-cell gate's accumulated displacement and, with
+// MCL_INTEGER_SHIFT, the per-channel whole-cell shifts and carried remainders
+// (written to the device on stream s).  *launch says whether a warp happens.
+// The arithmetic is FP64 in the order of the displacement formula
+// R(psi_k) [u, v] / cell with psi_k = theta + k 2 pi / n_theta.
+static hipError_t plan_motion(mcl_filter f, double u, double v, double w, StepArgs& a, hipStream_t s,
+                              bool* launch) {
+  const double cell = f->map->cell;
+  const uint32_t flags = f->map->flags;
+  double mu = u, mv = v, th = f->theta;  // motion to warp by and the heading it is expressed at
+  *launch = true;
+  if (flags & MCL_SUBCELL_GATE) {
+    const double c = cos(f->theta), sn = sin(f->theta);
+    const double ax = f->acc_x + u * c - v * sn;
+    const double ay = f->acc_y + u * sn + v * c;
+    f->theta += w;
+    ++f->steps;
+    if (hypot(ax, ay) < cell) {
+      f->acc_x = ax;
+      f->acc_y = ay;
+      *launch = false;
+      return hipSuccess;
+    }
+    f->acc_x = f->acc_y = 0.0;
+    mu = ax;
+    mv = ay;
+    th = 0.0;
+  } else {
+    f->theta += w;
+    ++f->steps;
+  }
+  a.u_cells = mu / cell;
+  a.v_cells = mv / cell;
+  a.theta_prev = th;
+  a.ishift = nullptr;
+  if (flags & MCL_INTEGER_SHIFT) {
+    int32_t n[2 * kMaxTheta];
+    const double dth = 2.0 * M_PI / f->T;
+    for (int k = 0; k < f->T; ++k) {
+      const double psi = th + k * dth;
+      const double c = cos(psi), sn = sin(psi);
+      const double dx = (mu * c - mv * sn) / cell + f->rem[k][0];
+      const double dy = (mu * sn + mv * c) / cell + f->rem[k][1];
+      const double nx = floor(dx + 0.5), ny = floor(dy + 0.5);
+      f->rem[k][0] = dx - nx;
+      f->rem[k][1] = dy - ny;
+      n[2 * k] = static_cast<int32_t>(nx);
+      n[2 * k + 1] = static_cast<int32_t>(ny);
+    }
+    const hipError_t e = launch_write_shifts(n, f->T, f->ishift, s);
+    if (e != hipSuccess) return e;
+    a.ishift = f->ishift;
+  }
+  return hipSuccess;
+}
+
 mcl_status mcl_step_odometry(mcl_filter f, double u, double v, double w) {
   if (!f) return fail(MCL_EINVAL, "filter is NULL");
   if (!isfinite(u) || !isfinite(v) || !isfinite(w)) return fail(MCL_EINVAL, "odometry is not finite");
   const double cell = f->map->cell;
   if (fabs(u) / cell > 1e6 || fabs(v) / cell > 1e6) return fail(MCL_EINVAL, "odometry exceeds 1e6 cells");
   StepArgs a = make_step_args(f);
-  if (f->map->flags & MCL_SUBCELL_GATE) {
-    const double c = cos(f->theta), s = sin(f->theta);
-    const double ax = f->acc_x + u * c - v * s;
-    const double ay = f->acc_y + u * s + v * c;
-    f->theta += w;
-    ++f->steps;
-    if (hypot(ax, ay) < cell) {
-      f->acc_x = ax;
-      f->acc_y = ay;
-      return MCL_OK;
-    }
-    f->acc_x = f->acc_y = 0.0;
-    a.u_cells = ax / cell;
-    a.v_cells = ay / cell;
-    a.theta_prev = 0.0;
-  } else {
-    a.u_cells = u / cell;
-    a.v_cells = v / cell;
-    a.theta_prev = f->theta;
-    f->theta += w;
-    ++f->steps;
-  }
+  bool launch = false;
+  HIP_TRY(plan_motion(f, u, v, w, a, f->stream, &launch), "shift table");
+  if (!launch) return MCL_OK;
   HIP_TRY(launch_step(f->dtype, f->radius, f->shape.k, a, f->stream), "step launch");
   return MCL_OK;
 }
@@ -734,28 +777,9 @@ mcl_status mcl_step_batch(mcl_filter* const filters, const double* uvw, int32_t 
     const double u = uvw[3 * i], v = uvw[3 * i + 1], w = uvw[3 * i + 2];
     const double cell = f->map->cell;
     StepArgs a = make_step_args(f);
-    if (f->map->flags & MCL_SUBCELL_GATE) {
-      const double c = cos(f->theta), sn = sin(f->theta);
-      const double ax = f->acc_x + u * c - v * sn;
-      const double ay = f->acc_y + u * sn + v * c;
-      f->theta += w;
-      ++f->steps;
-      if (hypot(ax, ay) < cell) {
-        f->acc_x = ax;
-        f->acc_y = ay;
-        continue;
-      }
-      f->acc_x = f->acc_y = 0.0;
-      a.u_cells = ax / cell;
-      a.v_cells = ay / cell;
-      a.theta_prev = 0.0;
-    } else {
-      a.u_cells = u / cell;
-      a.v_cells = v / cell;
-      a.theta_prev = f->theta;
-      f->theta += w;
-      ++f->steps;
-    }
+    bool launch = false;
+    HIP_TRY(plan_motion(f, u, v, w, a, static_cast<hipStream_t>(stream), &launch), "shift table");
+    if (!launch) continue;
     jobs.push_back(Job{a, f->dtype, f->radius, f->shape.k});
   }
   if (jobs.empty()) return MCL_OK;

@@ -227,6 +227,14 @@ __global__ void belief_map_kernel(const T* __restrict__ buf, int W, int H, int p
   out[static_cast<int64_t>(y) * W + x] = static_cast<float>(static_cast<double>(m) / dev->aux[3]);
 }
 
+struct ShiftList {
+  int32_t n[2 * kMaxTheta];
+};
+
+__global__ void write_shifts_kernel(ShiftList l, int count, int32_t* __restrict__ dst) {
+  for (int i = threadIdx.x; i < 2 * count; i += blockDim.x) dst[i] = l.n[i];
+}
+
 __global__ void dev_init_kernel(FilterDev* dev, double sum, float maxval) {
   FilterDev d = {};
   d.log_norm = 0.0;
@@ -328,6 +336,14 @@ hipError_t launch_export(int dtype, const void* buf, int W, int H, int pitch, in
       default: return hipErrorInvalidValue;
     }
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_write_shifts(const int32_t* n, int count, int32_t* dst, hipStream_t s) {
+  if (count < 1 || count > kMaxTheta) return hipErrorInvalidValue;
+  ShiftList l;
+  for (int i = 0; i < 2 * count; ++i) l.n[i] = n[i];
+  hipLaunchKernelGGL(write_shifts_kernel, dim3(1), dim3(256), 0, s, l, count, dst);
   return hipGetLastError();
 }
 

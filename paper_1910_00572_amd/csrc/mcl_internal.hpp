@@ -84,6 +84,7 @@ struct StepArgs {
   double theta_prev, dtheta;  // heading offset before the step, 2 pi / n_theta
   float gxy[kMaxTaps];        // x/y taps, centred at index R of the kernel radius
   float gth[kMaxTaps];        // theta taps
+  const int32_t* ishift;      // whole-cell shifts (nx, ny) per channel, or null: computed from u, v
 };
 
 // Gaussian taps of the map's x/y blur (FP64, index m + radius).
@@ -167,6 +168,9 @@ hipError_t launch_export(int dtype, const void* buf, int W, int H, int pitch, in
                          int64_t sstride, const FilterDev* dev, float* out, int64_t out_slice_stride,
                          int k_begin, int k_end, float* map_out, hipStream_t s);
 hipError_t launch_dev_init(FilterDev* dev, double sum, float maxval, hipStream_t s);
+// Write n[0 .. 2*count) (whole-cell shifts, nx ny per channel) to device memory
+// through the kernel's arguments: no host-side synchronisation.
+hipError_t launch_write_shifts(const int32_t* n, int count, int32_t* dst, hipStream_t s);
 
 // Floyd-Steinberg sample selection (sample.hip).  src: H x W dense FP32,
 // either the intensity itself (scaled == false) or the belief map, turned into

@@ -207,8 +207,16 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int blk, cons
   const double u = a.u_cells, v = a.v_cells, th0 = a.theta_prev, dth = a.dtheta;
 
   // Per-channel displacement R(theta + k dtheta) [u, v] in cells, split into
-  // integer and fractional parts (FP64, once per workgroup).
+  // integer and fractional parts (FP64, once per workgroup); or whole-cell
+  // shifts given by the host.
   for (int k = t; k < nth; k += NT) {
+    if (a.ishift) {
+      pnx[k] = a.ishift[2 * k];
+      pny[k] = a.ishift[2 * k + 1];
+      pfx[k] = 0.f;
+      pfy[k] = 0.f;
+      continue;
+    }
     double sn, cs;
     sincos(th0 + k * dth, &sn, &cs);
     const double dx = u * cs - v * sn;
@@ -596,6 +604,13 @@ __device__ __forceinline__ void stream_body(const StepArgs& a, const int blk, co
   const double u = a.u_cells, v = a.v_cells, th0 = a.theta_prev, dth = a.dtheta;
 
   for (int k = t; k < nth; k += NT) {
+    if (a.ishift) {
+      pnx[k] = a.ishift[2 * k];
+      pny[k] = a.ishift[2 * k + 1];
+      pfx[k] = 0.f;
+      pfy[k] = 0.f;
+      continue;
+    }
     double sn, cs;
     sincos(th0 + k * dth, &sn, &cs);
     const double dx = u * cs - v * sn;

@@ -17,7 +17,7 @@ _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libmcl.so"
 
 F32, BF16, F16 = 0, 1, 2
 DTYPES = {"f32": F32, "bf16": BF16, "f16": F16}
-MASK_BEFORE_BLUR, WALL_NORMALIZE, SUBCELL_GATE, SCAN_F32 = 1, 2, 4, 8
+MASK_BEFORE_BLUR, WALL_NORMALIZE, SUBCELL_GATE, SCAN_F32, INTEGER_SHIFT = 1, 2, 4, 8, 16
 DEFAULT_FLAGS = MASK_BEFORE_BLUR | WALL_NORMALIZE
 OK, EINVAL, ENOMEM, EDEGENERATE, EDEVICE, ESTATE = range(6)
 STATUS_NAMES = {0: "MCL_OK", 1: "MCL_EINVAL", 2: "MCL_ENOMEM", 3: "MCL_EDEGENERATE",

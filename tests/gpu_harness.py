@@ -31,7 +31,8 @@ def say(msg):
 def oracle_params(n_theta, cell, sxy, sth, rxy=-1, rth=-1, flags=3):
     return O.OracleParams(n_theta=n_theta, cell_m=cell, sigma_xy=sxy, sigma_theta=sth, radius_xy=rxy,
                           radius_theta=rth, mask_before_blur=bool(flags & 1),
-                          wall_normalize=bool(flags & 2), subcell_gate=bool(flags & 4))
+                          wall_normalize=bool(flags & 2), subcell_gate=bool(flags & 4),
+                          integer_shift=bool(flags & 16))
 
 
 def make_gpu(occ, cell, n_theta, sxy, sth, rxy=-1, rth=-1, storage="f32", flags=3, init=None, theta0=0.0,

@@ -65,6 +65,16 @@ def test_multi_tile_map_with_theta_chunks():
     _run_pair(occ, 0.1, 40, 1.0, 1.0, odo, check_every=5, tag="multitile")
 
 
+@pytest.mark.parametrize("shape", ["64,16,256,0", "32,16,128,0", "0,8,256,1,2", "0,12,256,2,2", "0,16,256,1,2",
+                                   "0,8,512,1,1", "0,16,512,1,1"])
+def test_every_kernel_shape(shape, monkeypatch):
+    # the launch shape is chosen when the filter is created; each one must match the oracle
+    monkeypatch.setenv("MCL_STEP_SHAPE", shape)
+    occ = bsp_rooms(150, 70, seed=9)
+    odo = random_odometry(12, seed=10, max_step_m=0.2) - np.array([0.1, 0.1, 0.0])
+    _run_pair(occ, 0.1, 40, 1.0, 1.0, odo, check_every=4, tag=f"shape {shape}")
+
+
 @pytest.mark.parametrize("n_theta", [1, 2, 3, 5])
 def test_few_heading_channels_wrap(n_theta):
     occ = bsp_rooms(40, 33, seed=11)
@@ -91,7 +101,7 @@ def test_zero_noise_integer_shift_is_exact():
     assert b[0, 9, 8] == 1.0 and pose.as_tuple() == (0, 9, 8)
 
 
-@pytest.mark.parametrize("flags", [1, 2, 0, 1 | 2 | 4])
+@pytest.mark.parametrize("flags", [1, 2, 0, 1 | 2 | 4, 1 | 2 | 16, 1 | 2 | 4 | 16, 16])
 def test_flags(flags):
     occ = bsp_rooms(48, 41, seed=15)
     odo = random_odometry(15, seed=16, max_step_m=0.08)

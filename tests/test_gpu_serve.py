@@ -44,6 +44,28 @@ def test_step_batch_is_bitwise_identical_to_single_steps():
         assert a.info().log_norm == b.info().log_norm
 
 
+def test_step_batch_with_gate_and_whole_cell_warp():
+    # filters whose maps use the sub-cell gate and the whole-cell warp with a
+    # carried remainder: the batch keeps each filter's host state, so the
+    # result is bitwise that of stepping alone (some filters skip launches)
+    from paper_1910_00572_amd import mcl
+    occs = [bsp_rooms(size, size, seed=70 + n) for n, size in enumerate((40, 56))]
+    flags = [mcl.DEFAULT_FLAGS | mcl.INTEGER_SHIFT, mcl.DEFAULT_FLAGS | mcl.INTEGER_SHIFT | mcl.SUBCELL_GATE]
+    maps = [mcl.Map(o, 0.1, 0.7, flags=fl) for o in occs for fl in flags]
+    solo = [mcl.Filter(m, 8 + 2 * i, 0.7, storage="f32") for i, m in enumerate(maps)]
+    batch = [mcl.Filter(m, 8 + 2 * i, 0.7, storage="f32") for i, m in enumerate(maps)]
+    ws = mcl.BatchWorkspace(len(maps))
+    odo = [random_odometry(15, seed=80 + i, max_step_m=0.06) for i in range(len(maps))]
+    say("[serve] step_batch vs single, whole-cell warp")
+    for t in range(15):
+        for i, f in enumerate(solo):
+            f.step_odometry(*odo[i][t])
+        mcl.step_batch(batch, np.stack([o[t] for o in odo]), ws)
+    for a, b in zip(solo, batch):
+        assert np.array_equal(a.export_belief().cpu().numpy(), b.export_belief().cpu().numpy())
+        assert a.info().log_norm == b.info().log_norm
+
+
 def test_server_mix_equals_alone_and_respects_budget():
     from paper_1910_00572_amd import mcl
     from paper_1910_00572_amd.serve import Request, Server, run_alone
