@@ -14,6 +14,8 @@ from .filter import (
     FilterState,
     OracleParams,
     gaussian_taps,
+    rotated_taps,
+    conv2d,
     default_radius,
     free_mask,
     kernel_activation,
@@ -37,6 +39,8 @@ __all__ = [
     "FilterState",
     "OracleParams",
     "gaussian_taps",
+    "rotated_taps",
+    "conv2d",
     "default_radius",
     "free_mask",
     "kernel_activation",

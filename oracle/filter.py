@@ -45,9 +45,14 @@ class OracleParams:
     wall_normalize: bool = True     # Alg. 1, division by the kernel activation
     subcell_gate: bool = False      # Alg. 1, "IF |u_{t,k}| >= 1"
     integer_shift: bool = False     # whole-cell warp with a per-channel remainder carry
+    sigma_lateral: float = -1.0     # >= 0: anisotropic noise, sigma_xy along the heading, this across
 
     def rxy(self) -> int:
-        return default_radius(self.sigma_xy) if self.radius_xy < 0 else self.radius_xy
+        if self.radius_xy >= 0:
+            return self.radius_xy
+        if self.sigma_lateral >= 0:
+            return default_radius(max(self.sigma_xy, self.sigma_lateral))
+        return default_radius(self.sigma_xy)
 
     def rth(self) -> int:
         return default_radius(self.sigma_theta) if self.radius_theta < 0 else self.radius_theta
@@ -137,6 +142,34 @@ def blur_theta(s: np.ndarray, g: np.ndarray) -> np.ndarray:
     out = np.zeros_like(s)
     for m in range(-r, r + 1):
         out += g[m + r] * np.roll(s, m, axis=0)
+    return out
+
+
+def rotated_taps(sigma_f: float, sigma_l: float, radius: int, psi: float) -> np.ndarray:
+    """2-D taps of the heading-rotated Gaussian (eq. Gaussian kernel and its covariance), summing to 1.
+
+    Covariance R(psi) diag(sigma_f^2, sigma_l^2) R(psi)^T: sigma_f along the
+    heading (cos psi, sin psi), sigma_l across it.  Tap [n + r, m + r] is the
+    weight of the displacement (m, n) = (dx, dy) in cells, |m|, |n| <= radius.
+    """
+    c, s = math.cos(psi), math.sin(psi)
+    g = np.zeros((2 * radius + 1, 2 * radius + 1))
+    for n in range(-radius, radius + 1):
+        for m in range(-radius, radius + 1):
+            a = c * m + s * n     # along the heading
+            b = -s * m + c * n    # across it
+            q = a * a / (sigma_f * sigma_f) + b * b / (sigma_l * sigma_l)
+            g[n + radius, m + radius] = math.exp(-0.5 * q)
+    return g / g.sum()
+
+
+def conv2d(s: np.ndarray, g: np.ndarray) -> np.ndarray:
+    """out(i, j) = sum_{m, n} g[n + r, m + r] s(i - m, j - n) on an (H, W) plane, zero outside."""
+    r = (g.shape[0] - 1) // 2
+    out = np.zeros_like(s)
+    for n in range(-r, r + 1):
+        for m in range(-r, r + 1):
+            out += g[n + r, m + r] * _translate(_translate(s, m, axis=-1), n, axis=-2)
     return out
 
 
@@ -267,8 +300,11 @@ def step(state: FilterState, occupancy: np.ndarray, p: OracleParams, u: float, v
         S[k] = shift_bilinear(state.B[k], dx[k], dy[k])
     if p.mask_before_blur:
         S = S * M
-    T = blur_theta(blur_y(blur_x(S, g_xy), g_xy), g_th)
-    U = T * Wt
+    if p.sigma_lateral >= 0:
+        U = _anisotropic_blur(S, M, p, g_th, state.theta)
+    else:
+        T = blur_theta(blur_y(blur_x(S, g_xy), g_xy), g_th)
+        U = T * Wt
     total = float(U.sum())
     if not (total > 0.0) or not math.isfinite(total):
         ns.B = state.B.copy()
@@ -277,6 +313,28 @@ def step(state: FilterState, occupancy: np.ndarray, p: OracleParams, u: float, v
     ns.B = U / total
     ns.log_norm = state.log_norm + math.log(total)
     return ns
+
+
+def _anisotropic_blur(S, M, p, g_th, theta):
+    """Anisotropic, heading-rotated motion noise (eq. Gaussian kernel with its rotated covariance).
+
+    The kernel of output channel k is the 2-D Gaussian rotated to that
+    channel's heading psi_k = theta + k delta_Theta (the heading its motion
+    was rotated by) times the theta Gaussian, so the theta blur runs first and
+    each channel then gets its own 2-D blur.  The kernel activation G(B_0, k)
+    depends on k: the channel's 2-D blur of M times the sum of the theta taps.
+    Then the post-blur mask and M / G(B_0, k) as in Alg. 1.
+    """
+    r = p.rxy()
+    dth = 2.0 * math.pi / p.n_theta
+    T = blur_theta(S, g_th)
+    U = np.empty_like(S)
+    for k in range(p.n_theta):
+        g = rotated_taps(p.sigma_xy, p.sigma_lateral, r, theta + k * dth)
+        Tk = conv2d(T[k], g)
+        Ak = conv2d(M, g) * g_th.sum()
+        U[k] = Tk * wall_weights(M, Ak, p.wall_normalize)
+    return U
 
 
 def run(occupancy: np.ndarray, p: OracleParams, odometry, state: FilterState | None = None,

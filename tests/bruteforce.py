@@ -46,7 +46,7 @@ class DenseModel:
     """Explicit matrices for one map and one set of noise parameters."""
 
     def __init__(self, occ, n_theta, sigma_xy, r_xy, sigma_th, r_th, wall_normalize=True,
-                 mask_before_blur=True):
+                 mask_before_blur=True, sigma_lateral=None, theta=0.0):
         self.occ = np.asarray(occ)
         self.H, self.W = self.occ.shape
         self.T = n_theta
@@ -54,6 +54,8 @@ class DenseModel:
         self.mask = np.tile((self.occ == 0).astype(np.float64).reshape(-1), n_theta)
         self.wall_normalize = wall_normalize
         self.mask_before_blur = mask_before_blur
+        self.sigma_lateral = sigma_lateral
+        self.theta = theta
         self.K = self._kernel_matrix(sigma_xy, r_xy, sigma_th, r_th)
         A = self.K @ self.mask
         self.post = np.where(self.mask > 0, self.mask / np.where(A > 0, A, 1.0), 0.0) \
@@ -62,25 +64,39 @@ class DenseModel:
     def idx(self, k, j, i):
         return (k * self.H + j) * self.W + i
 
-    def _kernel_matrix(self, sxy, rxy, sth, rth):
+    def _box(self, psi, sx, sy, sth, rxy, rth):
         box = []
         for dk in range(-rth, rth + 1):
             for dy in range(-rxy, rxy + 1):
                 for dx in range(-rxy, rxy + 1):
-                    q = _quad_form((dx, dy, dk), 0.37, sxy, sxy, sth)
+                    q = _quad_form((dx, dy, dk), psi, sx, sy, sth)
                     box.append((dx, dy, dk, 0.0 if math.isinf(q) else math.exp(-0.5 * q)))
         z = sum(b[3] for b in box)
+        return [(dx, dy, dk, w / z) for dx, dy, dk, w in box]
+
+    def _kernel_matrix(self, sxy, rxy, sth, rth):
+        # isotropic: one box (its rotation is immaterial); anisotropic: the box of
+        # each *target* channel, with the covariance R(psi) diag(s^2) R(psi)^T of
+        # that channel's heading psi (passed as -psi to the R_z^T D R_z form)
+        dth = 2.0 * math.pi / self.T
+        if self.sigma_lateral is None:
+            boxes = [self._box(0.37, sxy, sxy, sth, rxy, rth)] * self.T
+        else:
+            boxes = [self._box(-(self.theta + tk * dth), sxy, self.sigma_lateral, sth, rxy, rth)
+                     for tk in range(self.T)]
         K = np.zeros((self.n, self.n))
         for k in range(self.T):
             for j in range(self.H):
                 for i in range(self.W):
                     src = self.idx(k, j, i)
-                    for dx, dy, dk, wgt in box:
-                        if wgt == 0.0:
-                            continue
-                        ti, tj, tk = i + dx, j + dy, (k + dk) % self.T
-                        if 0 <= ti < self.W and 0 <= tj < self.H:
-                            K[self.idx(tk, tj, ti), src] += wgt / z
+                    for dk in range(-rth, rth + 1):
+                        tk = (k + dk) % self.T
+                        for dx, dy, ddk, wgt in boxes[tk]:
+                            if ddk != dk or wgt == 0.0:
+                                continue
+                            ti, tj = i + dx, j + dy
+                            if 0 <= ti < self.W and 0 <= tj < self.H:
+                                K[self.idx(tk, tj, ti), src] += wgt
         return K
 
     def push_matrix(self, u, v, theta, cell):
