@@ -55,10 +55,15 @@ enum {
   MCL_WALL_NORMALIZE = 2u,   /* divide by the kernel activation G(B_0) after the blur */
   MCL_SUBCELL_GATE = 4u,     /* accumulate motion until it reaches one cell (Alg. 1 IF) */
   MCL_SCAN_F32 = 8u,         /* scan cross term on FP32 operands instead of BF16 */
-  MCL_INTEGER_SHIFT = 16u    /* warp by whole cells: each channel moves by its displacement plus the
+  MCL_INTEGER_SHIFT = 16u,   /* warp by whole cells: each channel moves by its displacement plus the
                                 remainder it carries, rounded half up (floor(d + 1/2)), and carries
                                 d - floor(d + 1/2) to the next warp; with MCL_SUBCELL_GATE the warp
                                 happens when the gate fires */
+  MCL_ANISOTROPIC = 32u      /* motion noise with covariance R(psi_k) diag(sf^2, sl^2) R(psi_k)^T
+                                rotated to each channel's pre-step heading psi_k (eq. Gaussian
+                                kernel): sf = sigma_xy_cells along the heading, sl =
+                                sigma_lateral_cells across it; the theta blur runs first, then
+                                each channel's 2-D blur, with its own kernel activation G(B_0, k) */
 };
 
 typedef struct {
@@ -80,6 +85,9 @@ typedef struct {
   int32_t radius_theta;         /* blur half-width in bins;  < 0 => ceil(3 sigma) */
   mcl_dtype storage;            /* belief storage type; arithmetic is always FP32 */
   uint32_t flags;               /* MCL_* flags above */
+  double sigma_lateral_cells;   /* MCL_ANISOTROPIC: noise std-dev across the heading, cells, > 0
+                                   (sigma_xy_cells is then the std-dev along it, > 0; the 2-D
+                                   kernel radius is radius_xy, or ceil(3 max(sf, sl)), at most 6) */
 } mcl_params;
 
 typedef struct {

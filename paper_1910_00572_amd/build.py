@@ -19,7 +19,7 @@ CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libmcl.so")
-SOURCES = ["step.hip", "aux.hip", "scan.hip", "sample.hip", "api.cpp"]
+SOURCES = ["step.hip", "aux.hip", "scan.hip", "sample.hip", "aniso.hip", "api.cpp"]
 ARCH = "gfx950"
 
 

@@ -60,13 +60,29 @@ void gaussian_taps(double sigma, int radius, double* g) {
 
 size_t dtype_bytes(int dt) { return dt == MCL_F32 ? 4 : 2; }
 
+// Radius of the rotated 2-D kernel (MCL_ANISOTROPIC).
+int aniso_radius(const mcl_params* p) {
+  return p->radius_xy >= 0 ? p->radius_xy
+                           : static_cast<int>(ceil(3.0 * std::max(p->sigma_xy_cells, p->sigma_lateral_cells)));
+}
+
 mcl_status check_params(const mcl_params* p, bool need_theta) {
   if (!p) return fail(MCL_EINVAL, "params is NULL");
   if (!(p->sigma_xy_cells >= 0.0) || !isfinite(p->sigma_xy_cells))
     return fail(MCL_EINVAL, "sigma_xy_cells must be finite and >= 0");
-  const int rxy = resolve_radius(p->sigma_xy_cells, p->radius_xy);
-  if (rxy > kMaxRadius) return fail(MCL_EINVAL, "xy blur radius %d exceeds %d", rxy, kMaxRadius);
-  if (p->flags & ~0x1Fu) return fail(MCL_EINVAL, "unknown flags 0x%x", p->flags);
+  if (p->flags & ~0x3Fu) return fail(MCL_EINVAL, "unknown flags 0x%x", p->flags);
+  if (p->flags & MCL_ANISOTROPIC) {
+    // the map keeps only sigma_xy; the filter brings the lateral std-dev
+    if (need_theta) {
+      if (!(p->sigma_xy_cells > 0.0) || !(p->sigma_lateral_cells > 0.0) || !isfinite(p->sigma_lateral_cells))
+        return fail(MCL_EINVAL, "anisotropic noise needs sigma_xy_cells > 0 and sigma_lateral_cells > 0");
+      const int ra = aniso_radius(p);
+      if (ra > kAnisoMaxRadius) return fail(MCL_EINVAL, "2-D blur radius %d exceeds %d", ra, kAnisoMaxRadius);
+    }
+  } else {
+    const int rxy = resolve_radius(p->sigma_xy_cells, p->radius_xy);
+    if (rxy > kMaxRadius) return fail(MCL_EINVAL, "xy blur radius %d exceeds %d", rxy, kMaxRadius);
+  }
   if (need_theta) {
     if (p->n_theta < 1 || p->n_theta > kMaxTheta)
       return fail(MCL_EINVAL, "n_theta must be in [1, %d]", kMaxTheta);
@@ -147,6 +163,10 @@ struct mcl_filter_s {
   double acc_x = 0.0, acc_y = 0.0;
   double rem[kMaxTheta][2] = {};  // carried remainders of the whole-cell warp, cells
   int32_t* ishift = nullptr;      // device: whole-cell shifts of the current warp
+  float* aniso_tmp = nullptr;     // MCL_ANISOTROPIC: FP32 scratch of the theta-blurred tensor
+  double sf = 0.0, sl = 0.0;      // MCL_ANISOTROPIC: std-devs along / across the heading
+  int raniso = 0;                 // MCL_ANISOTROPIC: 2-D kernel radius
+  double gth_sum = 1.0;           // sum of the theta taps
   int64_t steps = 0;
   StepShape shape;
   float gxy[kMaxTaps] = {};
@@ -283,10 +303,12 @@ size_t carve_filter(mcl_filter f, void* ws, const mcl_map m, const mcl_params* p
   float* staging = static_cast<float*>(c.take(static_cast<size_t>(m->W) * m->H * sizeof(float)));
   const int R = std::max(1, std::max(m->rxy, resolve_radius(p->sigma_theta_bins, p->radius_theta)));
   const StepShape sh = choose_shape(m->W, m->H, p->n_theta, R, eb);
-  const int np = std::max(sh.blocks(), std::max(kReduceBlocks, kScanMaxBlocks(m->W, m->H, m->pitch)));
+  int np = std::max(sh.blocks(), std::max(kReduceBlocks, kScanMaxBlocks(m->W, m->H, m->pitch)));
+  if (p->flags & MCL_ANISOTROPIC) np = std::max(np, aniso_workgroups(m->W, m->H, p->n_theta));
   double* partials = static_cast<double*>(c.take(static_cast<size_t>(np) * 3 * sizeof(double)));
   FilterDev* dev = static_cast<FilterDev*>(c.take(kDevRegionBytes));
   int32_t* ishift = static_cast<int32_t*>(c.take(2 * kMaxTheta * sizeof(int32_t)));
+  float* atmp = (p->flags & MCL_ANISOTROPIC) ? static_cast<float*>(c.take(n * sizeof(float))) : nullptr;
   float* scratch = nullptr;
   int32_t* samp = nullptr;
   if (m->scan.n_dirs > 0) {
@@ -304,6 +326,7 @@ size_t carve_filter(mcl_filter f, void* ws, const mcl_map m, const mcl_params* p
     f->scan_scratch = scratch;
     f->samp_list = samp;
     f->ishift = ishift;
+    f->aniso_tmp = atmp;
     f->scanw = scan_work_carve(scanw, p->n_theta, m->scan.kpad);
     f->sstride = sstride;
     f->shape = sh;
@@ -359,7 +382,9 @@ mcl_status mcl_map_create(const mcl_map_desc* d, const mcl_params* p, void* ws, 
   m->H = d->height;
   m->cell = d->cell_m;
   m->sigma_xy = p->sigma_xy_cells;
-  m->rxy = resolve_radius(p->sigma_xy_cells, p->radius_xy);
+  // the isotropic wall weights the map keeps are not used by anisotropic
+  // filters, which compute their own activation per channel
+  m->rxy = std::min(kMaxRadius, resolve_radius(p->sigma_xy_cells, p->radius_xy));
   m->flags = p->flags;
   m->stream = static_cast<hipStream_t>(stream);
   carve_map(m, ws, d, p);
@@ -401,7 +426,8 @@ mcl_status mcl_init_belief(mcl_map map, const mcl_params* p, void* ws, size_t ws
   if (!map || !out) return fail(MCL_EINVAL, "map or out is NULL");
   mcl_status st = check_params(p, true);
   if (st != MCL_OK) return st;
-  if (p->sigma_xy_cells != map->sigma_xy || resolve_radius(p->sigma_xy_cells, p->radius_xy) != map->rxy ||
+  if (p->sigma_xy_cells != map->sigma_xy ||
+      std::min(kMaxRadius, resolve_radius(p->sigma_xy_cells, p->radius_xy)) != map->rxy ||
       p->flags != map->flags)
     return fail(MCL_EINVAL, "sigma_xy / radius_xy / flags differ from the map's");
   if (!isfinite(theta0)) return fail(MCL_EINVAL, "theta0 is not finite");
@@ -435,6 +461,13 @@ mcl_status mcl_init_belief(mcl_map map, const mcl_params* p, void* ws, size_t ws
   for (int m = -map->rxy; m <= map->rxy; ++m) f->gxy[f->radius + m] = static_cast<float>(g[m + map->rxy]);
   gaussian_taps(f->sigma_th, f->rth, g);
   for (int m = -f->rth; m <= f->rth; ++m) f->gth[f->radius + m] = static_cast<float>(g[m + f->rth]);
+  f->gth_sum = 0.0;
+  for (int m = 0; m <= 2 * f->rth; ++m) f->gth_sum += g[m];
+  if (map->flags & MCL_ANISOTROPIC) {
+    f->sf = p->sigma_xy_cells;
+    f->sl = p->sigma_lateral_cells;
+    f->raniso = aniso_radius(p);
+  }
   if (!step_config_supported(f->dtype, f->radius, f->shape.k) ||
       (f->shape.k.tx == 0 && !stream_plane_ok(map->W, map->H, dtype_bytes(f->dtype)))) {
     delete f;
@@ -530,6 +563,39 @@ static hipError_t plan_motion(mcl_filter f, double u, double v, double w, StepAr
   return hipSuccess;
 }
 
+// Arguments of the anisotropic step from the fused step's (motion, buffers)
+// and the filter; theta_pre orients the noise (the heading before the step).
+static AnisoArgs make_aniso_args(mcl_filter f, const StepArgs& s, double theta_pre) {
+  AnisoArgs a = {};
+  const mcl_map m = f->map;
+  a.buf[0] = f->buf[0];
+  a.buf[1] = f->buf[1];
+  a.tmp = f->aniso_tmp;
+  a.mpre = m->mpre;
+  a.free8 = m->free8;
+  a.partials = f->partials;
+  a.dev = f->dev;
+  a.ishift = s.ishift;
+  a.W = m->W;
+  a.H = m->H;
+  a.pitch = m->pitch;
+  a.n_theta = f->T;
+  a.rxy = f->raniso;
+  a.rth = f->rth;
+  a.wall_normalize = (m->flags & MCL_WALL_NORMALIZE) ? 1 : 0;
+  a.sstride = f->sstride;
+  a.u_cells = s.u_cells;
+  a.v_cells = s.v_cells;
+  a.theta_prev = s.theta_prev;
+  a.dtheta = s.dtheta;
+  a.noise_theta = theta_pre;
+  a.sf = f->sf;
+  a.sl = f->sl;
+  a.gth_sum = f->gth_sum;
+  for (int l = -f->rth; l <= f->rth; ++l) a.gth[l + f->rth] = f->gth[f->radius + l];
+  return a;
+}
+
 mcl_status mcl_step_odometry(mcl_filter f, double u, double v, double w) {
   if (!f) return fail(MCL_EINVAL, "filter is NULL");
   if (!isfinite(u) || !isfinite(v) || !isfinite(w)) return fail(MCL_EINVAL, "odometry is not finite");
@@ -537,8 +603,13 @@ mcl_status mcl_step_odometry(mcl_filter f, double u, double v, double w) {
   if (fabs(u) / cell > 1e6 || fabs(v) / cell > 1e6) return fail(MCL_EINVAL, "odometry exceeds 1e6 cells");
   StepArgs a = make_step_args(f);
   bool launch = false;
+  const double theta_pre = f->theta;
   HIP_TRY(plan_motion(f, u, v, w, a, f->stream, &launch), "shift table");
   if (!launch) return MCL_OK;
+  if (f->map->flags & MCL_ANISOTROPIC) {
+    HIP_TRY(launch_aniso_step(f->dtype, make_aniso_args(f, a, theta_pre), f->stream), "step launch");
+    return MCL_OK;
+  }
   HIP_TRY(launch_step(f->dtype, f->radius, f->shape.k, a, f->stream), "step launch");
   return MCL_OK;
 }
@@ -778,8 +849,15 @@ mcl_status mcl_step_batch(mcl_filter* const filters, const double* uvw, int32_t 
     const double cell = f->map->cell;
     StepArgs a = make_step_args(f);
     bool launch = false;
+    const double theta_pre = f->theta;
     HIP_TRY(plan_motion(f, u, v, w, a, static_cast<hipStream_t>(stream), &launch), "shift table");
     if (!launch) continue;
+    if (f->map->flags & MCL_ANISOTROPIC) {
+      // two plain passes of its own, on the batch stream
+      HIP_TRY(launch_aniso_step(f->dtype, make_aniso_args(f, a, theta_pre), static_cast<hipStream_t>(stream)),
+              "step launch");
+      continue;
+    }
     jobs.push_back(Job{a, f->dtype, f->radius, f->shape.k});
   }
   if (jobs.empty()) return MCL_OK;

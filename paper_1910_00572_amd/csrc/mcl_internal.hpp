@@ -87,6 +87,30 @@ struct StepArgs {
   const int32_t* ishift;      // whole-cell shifts (nx, ny) per channel, or null: computed from u, v
 };
 
+// Odometry step with anisotropic, heading-rotated noise (aniso.hip).
+constexpr int kAnisoMaxRadius = 6;  // 2-D kernel radius, cells
+struct AnisoArgs {
+  void* buf[2];
+  float* tmp;                 // FP32 scratch, [k][j][pitch]
+  const float* mpre;          // pre-blur traversability, [j][pitch]
+  const uint8_t* free8;       // free cells, [j][pitch] (0 outside the grid)
+  double* partials;           // 2 doubles per workgroup of the second pass
+  FilterDev* dev;
+  const int32_t* ishift;      // whole-cell shifts per channel, or null
+  int32_t W, H, pitch, n_theta;
+  int32_t rxy, rth;           // 2-D kernel radius; theta radius
+  int32_t wall_normalize;
+  int64_t sstride;
+  double u_cells, v_cells;    // motion to warp by, cells, at heading theta_prev
+  double theta_prev, dtheta;
+  double noise_theta;         // heading of channel 0 that orients the noise (pre-step)
+  double sf, sl;              // std-devs along and across the heading, cells
+  double gth_sum;             // sum of the theta taps
+  float gth[kMaxTaps];        // theta taps, index l + rth
+};
+hipError_t launch_aniso_step(int dtype, const AnisoArgs& a, hipStream_t s);
+int aniso_workgroups(int W, int H, int n_theta);
+
 // Gaussian taps of the map's x/y blur (FP64, index m + radius).
 struct MapTaps {
   double g[kMaxTaps];

@@ -17,7 +17,7 @@ _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libmcl.so"
 
 F32, BF16, F16 = 0, 1, 2
 DTYPES = {"f32": F32, "bf16": BF16, "f16": F16}
-MASK_BEFORE_BLUR, WALL_NORMALIZE, SUBCELL_GATE, SCAN_F32, INTEGER_SHIFT = 1, 2, 4, 8, 16
+MASK_BEFORE_BLUR, WALL_NORMALIZE, SUBCELL_GATE, SCAN_F32, INTEGER_SHIFT, ANISOTROPIC = 1, 2, 4, 8, 16, 32
 DEFAULT_FLAGS = MASK_BEFORE_BLUR | WALL_NORMALIZE
 OK, EINVAL, ENOMEM, EDEGENERATE, EDEVICE, ESTATE = range(6)
 STATUS_NAMES = {0: "MCL_OK", 1: "MCL_EINVAL", 2: "MCL_ENOMEM", 3: "MCL_EDEGENERATE",
@@ -42,7 +42,7 @@ class MapDesc(ctypes.Structure):
 class Params(ctypes.Structure):
     _fields_ = [("n_theta", c_int32), ("sigma_xy_cells", c_double), ("sigma_theta_bins", c_double),
                 ("radius_xy", c_int32), ("radius_theta", c_int32), ("storage", c_int32),
-                ("flags", c_uint32)]
+                ("flags", c_uint32), ("sigma_lateral_cells", c_double)]
 
 
 class Pose(ctypes.Structure):
@@ -141,9 +141,9 @@ def _stream_handle(stream):
 
 
 def _params(n_theta=1, sigma_xy=0.0, sigma_theta=0.0, radius_xy=-1, radius_theta=-1, storage="f32",
-            flags=DEFAULT_FLAGS) -> Params:
+            flags=DEFAULT_FLAGS, sigma_lateral=0.0) -> Params:
     return Params(int(n_theta), float(sigma_xy), float(sigma_theta), int(radius_xy), int(radius_theta),
-                  DTYPES[storage] if isinstance(storage, str) else int(storage), int(flags))
+                  DTYPES[storage] if isinstance(storage, str) else int(storage), int(flags), float(sigma_lateral))
 
 
 class Map:
@@ -188,14 +188,14 @@ class Filter:
     """One belief tensor on the GPU (init_belief)."""
 
     def __init__(self, map: Map, n_theta, sigma_theta, *, radius_theta=-1, storage="f32", init=None,
-                 theta0=0.0, stream=None):
+                 theta0=0.0, stream=None, sigma_lateral=0.0):
         import torch
         lib = load_library()
         self.map = map
         self.n_theta = int(n_theta)
         self.storage = storage
         self.params = _params(n_theta, map.sigma_xy, sigma_theta, map.radius_xy, radius_theta, storage,
-                              map.flags)
+                              map.flags, sigma_lateral)
         nbytes = lib.mcl_filter_workspace_bytes(map.handle, byref(self.params))
         if nbytes == 0:
             _check(lib.mcl_init_belief(map.handle, byref(self.params), None, 0, None, None, 0.0,

@@ -28,18 +28,20 @@ def say(msg):
     sys.stdout.flush()
 
 
-def oracle_params(n_theta, cell, sxy, sth, rxy=-1, rth=-1, flags=3):
+def oracle_params(n_theta, cell, sxy, sth, rxy=-1, rth=-1, flags=3, sigma_lateral=-1.0):
     return O.OracleParams(n_theta=n_theta, cell_m=cell, sigma_xy=sxy, sigma_theta=sth, radius_xy=rxy,
+                          sigma_lateral=sigma_lateral if flags & 32 else -1.0,
                           radius_theta=rth, mask_before_blur=bool(flags & 1),
                           wall_normalize=bool(flags & 2), subcell_gate=bool(flags & 4),
                           integer_shift=bool(flags & 16))
 
 
 def make_gpu(occ, cell, n_theta, sxy, sth, rxy=-1, rth=-1, storage="f32", flags=3, init=None, theta0=0.0,
-             range_table=None, max_range_m=0.0):
+             range_table=None, max_range_m=0.0, sigma_lateral=0.0):
     from paper_1910_00572_amd import mcl
     m = mcl.Map(occ, cell, sxy, radius_xy=rxy, flags=flags, range_table=range_table, max_range_m=max_range_m)
-    f = mcl.Filter(m, n_theta, sth, radius_theta=rth, storage=storage, init=init, theta0=theta0)
+    f = mcl.Filter(m, n_theta, sth, radius_theta=rth, storage=storage, init=init, theta0=theta0,
+                   sigma_lateral=sigma_lateral)
     return m, f
 
 

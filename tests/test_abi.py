@@ -31,12 +31,27 @@ def test_library_exports_every_declared_symbol():
         assert hasattr(lib, name), name
 
 
-def test_struct_layouts_match_header():
-    # offsets the C compiler gives these structs on x86-64 (natural alignment)
-    assert ctypes.sizeof(mcl.MapDesc) == 48
-    assert ctypes.sizeof(mcl.Params) == 40
-    assert ctypes.sizeof(mcl.Pose) == 48
-    assert mcl.Info.steps.offset == 40 and ctypes.sizeof(mcl.Info) == 88
+def test_struct_layouts_match_header(tmp_path):
+    # sizes and offsets the C compiler gives the header's structs, against the binding's
+    import subprocess
+    src = tmp_path / "layout.c"
+    src.write_text("""#include <stddef.h>
+#include <stdio.h>
+#include "mcl.h"
+int main(void) {
+  printf("%zu %zu %zu %zu %zu %zu %zu\\n", sizeof(mcl_map_desc), sizeof(mcl_params),
+         offsetof(mcl_params, sigma_lateral_cells), sizeof(mcl_pose), offsetof(mcl_info, steps),
+         offsetof(mcl_info, belief_device), sizeof(mcl_info));
+  return 0;
+}
+""")
+    exe = tmp_path / "layout"
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    subprocess.check_call(["gcc", "-I", inc, str(src), "-o", str(exe)])
+    got = [int(x) for x in subprocess.check_output([str(exe)]).split()]
+    assert got == [ctypes.sizeof(mcl.MapDesc), ctypes.sizeof(mcl.Params), mcl.Params.sigma_lateral_cells.offset,
+                   ctypes.sizeof(mcl.Pose), mcl.Info.steps.offset, mcl.Info.belief_device.offset,
+                   ctypes.sizeof(mcl.Info)]
 
 
 def test_argument_errors_before_any_device_work():

@@ -19,10 +19,12 @@ from tests.gpu_harness import (FP32_PEAK_TOL, FP32_TIE_TAU, in_tie_set, make_gpu
 pytestmark = [pytest.mark.gpu, needs_gpu]
 
 
-def _run_pair(occ, cell, n_theta, sxy, sth, odo, *, rxy=-1, rth=-1, flags=3, check_every=1, tag=""):
+def _run_pair(occ, cell, n_theta, sxy, sth, odo, *, rxy=-1, rth=-1, flags=3, check_every=1, tag="",
+              sigma_lateral=0.0, storage="f32"):
     say(f"[parity] {tag} map={occ.shape} T={n_theta} sxy={sxy} sth={sth} steps={len(odo)} flags={flags}")
-    _, f = make_gpu(occ, cell, n_theta, sxy, sth, rxy, rth, flags=flags)
-    p = oracle_params(n_theta, cell, sxy, sth, rxy, rth, flags)
+    _, f = make_gpu(occ, cell, n_theta, sxy, sth, rxy, rth, flags=flags, sigma_lateral=sigma_lateral,
+                    storage=storage)
+    p = oracle_params(n_theta, cell, sxy, sth, rxy, rth, flags, sigma_lateral=sigma_lateral)
     st = O.init_uniform(occ, n_theta)
     M = O.free_mask(occ)
     worst = 0.0
@@ -73,6 +75,51 @@ def test_every_kernel_shape(shape, monkeypatch):
     occ = bsp_rooms(150, 70, seed=9)
     odo = random_odometry(12, seed=10, max_step_m=0.2) - np.array([0.1, 0.1, 0.0])
     _run_pair(occ, 0.1, 40, 1.0, 1.0, odo, check_every=4, tag=f"shape {shape}")
+
+
+@pytest.mark.parametrize("case", [
+    # (map, n_theta, sigma along, sigma across, sigma theta, radius xy, flags)
+    ((48, 41), 16, 1.2, 0.4, 0.8, -1, 3 | 32),
+    ((37, 23), 12, 0.5, 1.3, 0.6, -1, 3 | 32),
+    ((64, 40), 8, 1.0, 0.3, 0.0, 2, 1 | 32),
+    ((48, 41), 10, 0.9, 0.5, 0.7, -1, 3 | 16 | 32),
+    ((40, 33), 6, 1.5, 0.6, 0.9, -1, 3 | 4 | 32),
+    ((90, 70), 36, 1.1, 0.5, 1.0, -1, 3 | 32),
+])
+def test_anisotropic_noise(case):
+    # heading-rotated anisotropic noise (two-pass kernels) against the oracle
+    (W, H), n_theta, sf, sl, sth, rxy, flags = case
+    occ = bsp_rooms(W, H, seed=W + H)
+    odo = random_odometry(12, seed=n_theta, max_step_m=0.12)
+    _run_pair(occ, 0.1, n_theta, sf, sth, odo, rxy=rxy, flags=flags, sigma_lateral=sl, check_every=3,
+              tag=f"aniso {case}")
+
+
+def test_anisotropic_isotropic_limit_matches_the_fused_step():
+    # sigma across = sigma along: the two-pass path computes the separable step
+    occ = bsp_rooms(56, 44, seed=77)
+    odo = random_odometry(6, seed=78)
+    from tests.gpu_harness import make_gpu as mk
+    _, a = mk(occ, 0.1, 12, 0.8, 0.7)
+    _, b = mk(occ, 0.1, 12, 0.8, 0.7, flags=3 | 32, sigma_lateral=0.8)
+    for u, v, w in odo:
+        a.step_odometry(u, v, w)
+        b.step_odometry(u, v, w)
+    ba, _, _, la = a.read_belief()
+    bb, _, _, lb = b.read_belief()
+    assert peak_err(bb, ba.astype(np.float64)) <= 2e-6
+    assert lb == pytest.approx(la, abs=1e-5)
+
+
+def test_anisotropic_parameter_errors():
+    from paper_1910_00572_amd import mcl
+    occ = bsp_rooms(32, 30, seed=79)
+    m = mcl.Map(occ, 0.1, 1.0, flags=3 | 32)
+    for kw in (dict(sigma_lateral=0.0), dict(sigma_lateral=-1.0), dict(sigma_lateral=float("nan")),
+               dict(sigma_lateral=2.5)):  # the last needs radius 8 > 6
+        with pytest.raises(mcl.MclError) as ei:
+            mcl.Filter(m, 8, 0.5, **kw)
+        assert ei.value.status == mcl.EINVAL
 
 
 @pytest.mark.parametrize("n_theta", [1, 2, 3, 5])
