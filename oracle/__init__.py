@@ -33,6 +33,7 @@ from .filter import (
     argmax_pose,
 )
 from .scan import quantize_ranges, beam_offsets, scan_sqdist, apply_scan
+from .difficulty import best_match, difficulty
 from .sample import dither_intensity, floyd_steinberg, floyd_steinberg_c, sample_mask, apply_scan_sampled
 
 __all__ = [
@@ -65,4 +66,6 @@ __all__ = [
     "floyd_steinberg_c",
     "sample_mask",
     "apply_scan_sampled",
+    "best_match",
+    "difficulty",
 ]
