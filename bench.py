@@ -277,6 +277,59 @@ def bench_integer_gate(n_steps=200, split=4):
     return out
 
 
+def bench_aniso(steps=100):
+    """512x512x72 FP32 with anisotropic heading-rotated noise (sigma 1.0 along, 0.5 across, radius 3)."""
+    import torch
+    from paper_1910_00572_amd import mcl
+    occ, odo = headline_inputs(steps + 10)
+    m = mcl.Map(occ, 0.05, 1.0, flags=mcl.DEFAULT_FLAGS | mcl.ANISOTROPIC)
+    f = mcl.Filter(m, 72, 1.0, storage="f32", sigma_lateral=0.5)
+    elapsed, lat = time_filter(f, odo, steps, 5, 20)
+    states = occ.size * 72
+    kern = float(lat.mean())
+    # two passes: read B, write the FP32 scratch; read it, write B
+    algo = 4 * states * 4
+    # per state: bilinear warp of 7 theta taps (7 x 4 FMA) + 49-tap blurs of the scratch and the mask
+    flops = 2 * states * (7 * 4 + 2 * 49)
+    out = {"states_steps_per_s": states * steps / elapsed, "ms_per_step": elapsed * 1e3 / steps,
+           "event_mean_ms": kern, "hbm_frac_two_pass_bytes": algo / (kern * 1e-3) / 1e9 / HBM_PEAK_GBS,
+           "fp32_frac_of_vector_peak": flops / (kern * 1e-3) / 78.6e12}
+    del f, m
+    torch.cuda.empty_cache()
+    return out
+
+
+def bench_match(grid=256, n_theta=72, batch=64):
+    """Map difficulty D_M on a grid x grid floor plan: the best match of a noisy
+    scan (360 beams, sigma 0.1 m) taken at every free cell, over every free state."""
+    import time
+    import torch
+    from gen import cell_scans, range_table, rooms_and_corridors
+    from paper_1910_00572_amd import mcl
+    occ = rooms_and_corridors(grid, grid, seed=5)
+    R = range_table(occ, 0.05, 360, 10.0)
+    m = mcl.Map(occ, 0.05, 1.0, range_table=R, max_range_m=10.0)
+    qcells = np.flatnonzero(occ.reshape(-1) == 0)
+    z = cell_scans(R, qcells, 0.1, 10.0, seed=6)
+    mcl.best_match(m, n_theta, z[:batch], batch=batch)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    cell, head, dist = mcl.best_match(m, n_theta, z, batch=batch)
+    elapsed = time.perf_counter() - t0
+    dm = mcl.difficulty(m, qcells, cell, 1.0)
+    pitch = (grid + 7) // 8 * 8  # row pitch: a multiple of 8 cells
+    cells_pad = (grid * pitch + 127) // 128 * 128
+    cols = sum(((min(batch, len(z) - q0) * n_theta + 31) // 32 * 32) for q0 in range(0, len(z), batch))
+    flops = 2.0 * cells_pad * 384 * cols
+    out = {"queries": int(len(z)), "seconds": elapsed, "queries_per_s": len(z) / elapsed,
+           "candidate_states": int(len(qcells) * n_theta), "D_M": dm,
+           "gemm_tflops_wall": flops / elapsed / 1e12,
+           "bf16_frac_of_mfma_peak_wall": flops / elapsed / 1e12 / 2500.0}
+    del m
+    torch.cuda.empty_cache()
+    return out
+
+
 def bench_serving(n_requests, seed=8, capacity=None):
     """Poisson stream of mixed filters (grid 128..1024, 36/72 bins, FP32/BF16, scans on half).
 
@@ -335,7 +388,7 @@ def main():
                     help="also run a plain device copy of this many MiB (counter calibration)")
     ap.add_argument("--serving-requests", type=int, default=256)
     ap.add_argument("--only", default="", help="comma-separated extra sections to run "
-                    "(mixed, scan, sampled, gate, serving); default all")
+                    "(mixed, scan, sampled, gate, aniso, difficulty, serving); default all")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: the filter step is a single-GPU kernel and this build "
@@ -400,7 +453,8 @@ def main():
     del f, m
     torch.cuda.empty_cache()
     if not args.no_extra:
-        only = set(x for x in args.only.split(",") if x) or {"mixed", "scan", "sampled", "gate", "serving"}
+        only = set(x for x in args.only.split(",") if x) or {"mixed", "scan", "sampled", "gate", "aniso",
+                                                                   "difficulty", "serving"}
         if "mixed" in only:
             log("[bench] 1024x1024x128 FP32 vs BF16")
             out["mixed_precision_1024x1024x128"] = bench_mixed_precision(100)
@@ -410,9 +464,15 @@ def main():
         if "sampled" in only:
             log("[bench] sampled update 512x512x72, 360 beams, 4096 samples")
             out["sampled_scan_512x512x72_360beams"] = bench_sampled(20)
+        if "aniso" in only:
+            log("[bench] anisotropic noise 512x512x72")
+            out["anisotropic_512x512x72"] = bench_aniso()
         if "gate" in only:
             log("[bench] whole-cell warp and sub-cell gate against bilinear, 512x512x72")
             out["whole_cell_warp_512x512x72"] = bench_integer_gate()
+        if "difficulty" in only:
+            log("[bench] map difficulty 256x256, 72 headings, every free cell queried")
+            out["map_difficulty_256x256x72_360beams"] = bench_match()
         if "serving" in only and args.serving_requests > 0:
             log(f"[bench] serving {args.serving_requests} requests")
             out["serving"] = bench_serving(args.serving_requests, capacity=value)

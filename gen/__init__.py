@@ -12,7 +12,7 @@ rooms, corridors, doorways and clutter at comparable sizes.
 
 from .maps import bsp_rooms, rooms_and_corridors, occupancy_fraction
 from .trajectory import random_odometry, smooth_trajectory
-from .raycast import range_table, scan_at, noisy_scan
+from .raycast import range_table, scan_at, noisy_scan, cell_scans
 
 __all__ = [
     "bsp_rooms",

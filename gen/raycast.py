@@ -67,3 +67,13 @@ def noisy_scan(occ, cell_m, pose, n_beams, max_range_m, sigma_m, seed) -> np.nda
     z = scan_at(occ, cell_m, pose[0], pose[1], pose[2], n_beams, max_range_m).astype(np.float64)
     z = z + rng.normal(0.0, sigma_m, n_beams)
     return np.clip(z, 0.0, max_range_m).astype(np.float32)
+
+
+def cell_scans(R: np.ndarray, cells, sigma_m: float, max_range_m: float, seed: int) -> np.ndarray:
+    """(len(cells), n_dirs) float32 scans taken at cell centres, heading 0: the
+    expected ranges R[cells] plus N(0, sigma_m) per beam, clamped to [0, max_range]."""
+    rng = np.random.default_rng(seed)
+    z = np.asarray(R, np.float64)[np.asarray(cells)]
+    if sigma_m > 0:
+        z = z + rng.normal(0.0, sigma_m, z.shape)
+    return np.clip(z, 0.0, max_range_m).astype(np.float32)

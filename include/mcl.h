@@ -237,6 +237,37 @@ mcl_status mcl_apply_scan_sampled(mcl_filter f, const float* ranges_m, int32_t n
 mcl_status mcl_dither(const float* dev_intensity, int32_t width, int32_t height, uint8_t* dev_mask,
                       void* stream);
 
+/* Device bytes mcl_best_match needs for batches of up to `batch` queries
+ * (0 if the map has no range table or the arguments are out of range). */
+size_t mcl_match_workspace_bytes(mcl_map map, int32_t n_theta, int32_t batch);
+
+/* best_match (sync): for each query scan, the state that matches it best
+ * (map difficulty, Sec. IV, localisation robustness): the free cell q and
+ * heading channel k with the smallest exact squared distance D of the scan
+ * update (as mcl_scan_sqdist, channel k at heading k 2 pi / n_theta, no
+ * heading offset), ties to the lowest k * H * W + q; occupied cells are not
+ * candidates.  ranges_m: host FP32 n_queries x n_dirs (metres, quantised as
+ * the scan update does).  out_cell: host int32 per query, j * W + i;
+ * out_heading, out_dist: host int32 per query (nullable).  Runs in batches of
+ * `batch` queries on the map's range table with dev_ws (caller-owned device
+ * memory of at least mcl_match_workspace_bytes(map, n_theta, batch) bytes).
+ * ESTATE without a range table; EINVAL for n_theta outside [1, 360], a table
+ * deeper than 384 directions, W * H >= 2^30, batch * n_theta columns of 2 GiB
+ * or more (batch * n_theta * 384 * 2 bytes for BF16 operands, * 4 for FP32),
+ * non-finite ranges or NULL pointers; ENOMEM for a small workspace. */
+mcl_status mcl_best_match(mcl_map map, int32_t n_theta, const float* ranges_m, int32_t n_queries,
+                          int32_t batch, int32_t* out_cell, int32_t* out_heading, int32_t* out_dist,
+                          void* dev_ws, size_t ws_bytes, void* stream);
+
+/* difficulty (host): D_M (Sec. IV), the fraction of the n query cells whose
+ * best match lies more than threshold_m metres from them (distance between
+ * cell centres, the map's cell size; a best cell of -1 counts as far).
+ * query_cells, best_cells: host int32 j * W + i.  EINVAL for NULL pointers
+ * with n > 0, n < 0, a query cell outside the map or a negative threshold;
+ * n == 0 gives 0. */
+mcl_status mcl_difficulty(mcl_map map, const int32_t* query_cells, const int32_t* best_cells, int32_t n,
+                          double threshold_m, double* out);
+
 /* Launch shape, sizes and scalars.  sync != 0 waits for the stream first so
  * log_norm and status are current. */
 mcl_status mcl_get_info(mcl_filter f, int sync, mcl_info* out);

@@ -807,6 +807,81 @@ mcl_status mcl_dither(const float* dev_intensity, int32_t width, int32_t height,
   return MCL_OK;
 }
 
+size_t mcl_match_workspace_bytes(mcl_map map, int32_t n_theta, int32_t batch) {
+  if (!map || map->scan.n_dirs == 0 || n_theta < 1 || n_theta > kMaxTheta || batch < 1 || batch > 65536) return 0;
+  return match_workspace_bytes(map->scan, map->H * map->pitch, n_theta, batch);
+}
+
+mcl_status mcl_best_match(mcl_map map, int32_t n_theta, const float* ranges_m, int32_t n_queries, int32_t batch,
+                          int32_t* out_cell, int32_t* out_heading, int32_t* out_dist, void* dev_ws,
+                          size_t ws_bytes, void* stream) {
+  if (!map) return fail(MCL_EINVAL, "map is NULL");
+  const ScanTable& t = map->scan;
+  if (t.n_dirs == 0) return fail(MCL_ESTATE, "the map has no range table");
+  if (n_theta < 1 || n_theta > kMaxTheta) return fail(MCL_EINVAL, "n_theta must be in [1, %d]", kMaxTheta);
+  if (t.kpad > 384) return fail(MCL_EINVAL, "best_match supports tables of at most 384 directions");
+  if (static_cast<int64_t>(map->W) * map->H >= (static_cast<int64_t>(1) << 30))
+    return fail(MCL_EINVAL, "best_match supports maps of fewer than 2^30 cells");
+  if (n_queries < 0 || batch < 1) return fail(MCL_EINVAL, "n_queries must be >= 0 and batch >= 1");
+  if (n_queries > 0 && (!ranges_m || !out_cell)) return fail(MCL_EINVAL, "NULL ranges or output");
+  const size_t need = mcl_match_workspace_bytes(map, n_theta, batch);
+  if (need == 0) return fail(MCL_EINVAL, "batch %d x %d channels is too large", batch, n_theta);
+  if (!dev_ws || ws_bytes < need) return fail(MCL_ENOMEM, "workspace of %zu bytes, %zu needed", ws_bytes, need);
+  const int N = t.n_dirs;
+  for (int64_t e = 0; e < static_cast<int64_t>(n_queries) * N; ++e)
+    if (!isfinite(ranges_m[e])) return fail(MCL_EINVAL, "range %lld is not finite", static_cast<long long>(e));
+  const double h = t.max_range / 256.0;
+  std::vector<int16_t> zq(static_cast<size_t>(batch) * N);
+  std::vector<int32_t> sz(batch);
+  std::vector<uint64_t> best(batch);
+  for (int q0 = 0; q0 < n_queries; q0 += batch) {
+    const int nq = std::min(batch, n_queries - q0);
+    for (int p = 0; p < nq; ++p) {
+      int32_t ss = 0;
+      for (int b = 0; b < N; ++b) {
+        double f = floor(static_cast<double>(ranges_m[static_cast<int64_t>(q0 + p) * N + b]) / h + 0.5);
+        f = f < 0.0 ? 0.0 : (f > 256.0 ? 256.0 : f);
+        const int q = static_cast<int>(f) - 128;
+        zq[static_cast<size_t>(p) * N + b] = static_cast<int16_t>(q);
+        ss += q * q;
+      }
+      sz[p] = ss;
+    }
+    HIP_TRY(match_launch(t, map->free8, map->W, map->H, map->pitch, n_theta, zq.data(), sz.data(), nq, dev_ws,
+                         best.data(), static_cast<hipStream_t>(stream)),
+            "best match");
+    for (int p = 0; p < nq; ++p) {
+      const uint64_t key = best[p];
+      const bool none = key == ~0ull;  // no free cell at all
+      out_cell[q0 + p] = none ? -1 : static_cast<int32_t>(key & ((1ull << 30) - 1));
+      if (out_heading) out_heading[q0 + p] = none ? -1 : static_cast<int32_t>((key >> 30) & 511u);
+      if (out_dist) out_dist[q0 + p] = none ? -1 : static_cast<int32_t>(key >> 39);
+    }
+  }
+  return MCL_OK;
+}
+
+mcl_status mcl_difficulty(mcl_map map, const int32_t* query_cells, const int32_t* best_cells, int32_t n,
+                          double threshold_m, double* out) {
+  if (!map || !out) return fail(MCL_EINVAL, "NULL map or output");
+  if (n < 0 || (n > 0 && (!query_cells || !best_cells))) return fail(MCL_EINVAL, "bad query list");
+  if (!(threshold_m >= 0.0)) return fail(MCL_EINVAL, "threshold must be >= 0");
+  const int64_t cells = static_cast<int64_t>(map->W) * map->H;
+  int64_t far = 0;
+  for (int32_t e = 0; e < n; ++e) {
+    const int64_t q = query_cells[e], b = best_cells[e];
+    if (q < 0 || q >= cells) return fail(MCL_EINVAL, "query cell %lld outside the map", static_cast<long long>(q));
+    if (b < 0 || b >= cells) {
+      ++far;
+      continue;
+    }
+    const double di = static_cast<double>(q % map->W - b % map->W), dj = static_cast<double>(q / map->W - b / map->W);
+    if (map->cell * hypot(di, dj) > threshold_m) ++far;
+  }
+  *out = n > 0 ? static_cast<double>(far) / n : 0.0;
+  return MCL_OK;
+}
+
 static size_t batch_bytes(int32_t n) {
   Carver c(nullptr);
   c.take(static_cast<size_t>(n) * sizeof(StepArgs));

@@ -823,6 +823,150 @@ __global__ __launch_bounds__(kScanThreads) void sampled_apply_kernel(SampledArgs
   }
 }
 
+// ---- best match of many scans over every free state (map difficulty) ------------------
+// For a batch of query scans, the free cell q and heading k whose expected scan
+// is closest (smallest exact D, heading offset 0): the dense product of the
+// range table with the circulant columns of every (query, heading), reduced by
+// min instead of exponentiated.  A 64-bit key (D, k, dense q) orders the
+// candidates as the stated tie rule does (lowest k * H * W + q), so one min
+// suffices: each workgroup takes the minimum over its cells per column, then
+// over the columns of one query, and folds it into best[query] with a 64-bit
+// atomic min (order-free, so the result does not depend on scheduling).
+struct MatchArgs {
+  const void* rq;          // MFMA-tiled range table
+  const int32_t* sr;       // [cells] sum of squares
+  const uint8_t* free8;    // [cells] free cells (pitch layout; 0 outside the grid)
+  const void* ct;          // [ncols_pad][kpad] circulant columns, column = query * n_theta + k
+  const int32_t* sz;       // [batch] sum of squared counts of each query
+  uint64_t* best;          // [batch], all ones before the launch
+  int32_t cells, pitch, W, n_theta, ncols, ncols_pad, kpad;
+  uint32_t rq_bytes;
+};
+
+constexpr uint64_t kNoKey = ~0ull;
+
+template <typename OP, int KPAD>
+__global__ __launch_bounds__(kScanThreads) void match_gemm_kernel(MatchArgs a) {
+  __shared__ uint64_t wmin[kScanThreads / 64][32];
+  constexpr int KSTEP = Mfma<OP>::KSTEP, HALF = Mfma<OP>::HALF, EB = sizeof(OP);
+  constexpr int KS = KPAD / KSTEP;
+  constexpr int PB = 8;  // B operand prefetch depth
+  using Vec = typename Mfma<OP>::Vec;
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  const int half = lane >> 5, col = lane & 31;
+  const int cell0 = blockIdx.x * kTileCells + wv * 32;
+  const int64_t ngroups = (a.cells + 31) / 32;
+  const uint32_t astep_bytes = static_cast<uint32_t>(ngroups * 64 * HALF * EB);
+  const __amdgpu_buffer_rsrc_t ra = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<void*>(a.rq), static_cast<short>(0), static_cast<int>(a.rq_bytes), 0x00020000);
+  const __amdgpu_buffer_rsrc_t rb = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<void*>(a.ct), static_cast<short>(0), static_cast<int>(a.ncols_pad * a.kpad * EB), 0x00020000);
+  // this wave's 32 cells: the A operand stays in registers for every column
+  Vec av[KS];
+  const uint32_t va = static_cast<uint32_t>(((cell0 >> 5) * 64 + lane) * HALF * EB);
+#pragma unroll
+  for (int st = 0; st < KS; ++st)
+    av[st] = __builtin_bit_cast(Vec, __builtin_amdgcn_raw_buffer_load_b128(ra, va, static_cast<uint32_t>(st) * astep_bytes, 0));
+  // the lane's 16 accumulator rows: sum of squares and the candidate part of the key
+  int srow[16];
+  uint64_t qrow[16];  // dense cell index, or kNoKey for cells that are not candidates
+#pragma unroll
+  for (int g = 0; g < 4; ++g) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int cell = cell0 + 8 * g + 4 * half + i;
+      const int j = cell / a.pitch, x = cell - j * a.pitch;
+      const bool ok = cell < a.cells && x < a.W && a.free8[min(cell, a.cells - 1)] != 0;
+      srow[4 * g + i] = a.sr[min(cell, a.cells - 1)];
+      qrow[4 * g + i] = ok ? static_cast<uint64_t>(j) * a.W + x : kNoKey;
+    }
+  }
+  for (int cb = 0; cb < a.ncols_pad / 32; ++cb) {
+    const uint32_t vb = static_cast<uint32_t>(((cb * 32 + col) * a.kpad + HALF * half) * EB);
+    Vec bbuf[PB];
+#pragma unroll
+    for (int u = 0; u < PB; ++u)
+      bbuf[u] = __builtin_bit_cast(Vec, __builtin_amdgcn_raw_buffer_load_b128(rb, vb, static_cast<uint32_t>(u * KSTEP * EB), 0));
+    f32x16 acc;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) acc[i] = 0.f;
+#pragma unroll
+    for (int st = 0; st < KS; ++st) {
+      Mfma<OP>::mma(av[st], bbuf[st % PB], acc);
+      __builtin_amdgcn_sched_barrier(0);
+      if (st + PB < KS)
+        bbuf[st % PB] = __builtin_bit_cast(
+            Vec, __builtin_amdgcn_raw_buffer_load_b128(rb, vb, static_cast<uint32_t>((st + PB) * KSTEP * EB), 0));
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    // column of this lane: query p, heading k
+    const int c = cb * 32 + col;
+    const bool cval = c < a.ncols;
+    const int p = cval ? c / a.n_theta : 0, k = cval ? c - p * a.n_theta : 0;
+    const int szp = a.sz[p];
+    uint64_t m = kNoKey;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const uint64_t d = static_cast<uint64_t>(szp - 2 * static_cast<int>(acc[r]) + srow[r]);
+      const uint64_t key = (qrow[r] == kNoKey || !cval) ? kNoKey : (d << 39) | (static_cast<uint64_t>(k) << 30) | qrow[r];
+      m = key < m ? key : m;
+    }
+    const uint64_t o = __shfl_xor(m, 32);  // the other 16 rows of the same column
+    m = o < m ? o : m;
+    if (half == 0) wmin[wv][col] = m;
+    __syncthreads();
+    if (wv == 0) {
+      // lanes 0..31: one column each; the columns of one query are contiguous
+      const int cc = cb * 32 + lane;
+      uint64_t b = kNoKey;
+      int q = -1;
+      if (lane < 32 && cc < a.ncols) {
+        b = wmin[0][lane];
+        for (int w = 1; w < kScanThreads / 64; ++w) b = wmin[w][lane] < b ? wmin[w][lane] : b;
+        q = cc / a.n_theta;
+      }
+      // segmented suffix minimum: lane t ends with the minimum of its query's lanes from t on
+#pragma unroll
+      for (int off = 1; off < 32; off <<= 1) {
+        const uint64_t ob = __shfl_down(b, off);
+        const int oq = __shfl_down(q, off);
+        if (lane + off < 64 && oq == q) b = ob < b ? ob : b;
+      }
+      const int pq = __shfl_up(q, 1);
+      if (q >= 0 && (lane == 0 || pq != q) && b != kNoKey)
+        __hip_atomic_fetch_min(a.best + q, b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __syncthreads();
+  }
+}
+
+// Circulant columns of a batch of queries: C[p * n_theta + k][beta] = zq_p[(beta - s_k) mod N].
+struct MatchCtArgs {
+  void* ct;
+  const int16_t* zq;        // [batch][n_dirs]
+  uint64_t* best;           // [nq], set to all ones
+  int32_t n_dirs, n_theta, ncols, ncols_pad, kpad, f32, nq;
+  int16_t s[kMaxTheta];
+};
+
+__global__ void match_ct_kernel(MatchCtArgs a) {
+  const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx < a.nq) a.best[idx] = kNoKey;
+  if (idx >= static_cast<int64_t>(a.ncols_pad) * a.kpad) return;
+  const int c = static_cast<int>(idx / a.kpad), beta = static_cast<int>(idx % a.kpad);
+  float v = 0.f;
+  if (c < a.ncols && beta < a.n_dirs) {
+    const int p = c / a.n_theta, k = c - p * a.n_theta;
+    int b = (beta - a.s[k]) % a.n_dirs;
+    if (b < 0) b += a.n_dirs;
+    v = static_cast<float>(a.zq[static_cast<int64_t>(p) * a.n_dirs + b]);
+  }
+  if (a.f32)
+    static_cast<float*>(a.ct)[idx] = v;
+  else
+    static_cast<__bf16*>(a.ct)[idx] = static_cast<__bf16>(v);
+}
+
 // ---- map table: quantise ranges ---------------------------------------------------------
 template <typename OP>
 __global__ void quantize_kernel(const float* __restrict__ src, OP* __restrict__ rq, int32_t* __restrict__ sr, int W,
@@ -1096,6 +1240,95 @@ hipError_t scan_sampled_launch(const ScanLaunch& L, const float* ranges_m, doubl
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+size_t match_workspace_bytes(const ScanTable& t, int cells, int n_theta, int batch) {
+  if (t.n_dirs == 0 || batch < 1) return 0;
+  (void)cells;
+  const int64_t ncols_pad = round_up_i(batch * n_theta, 32);
+  const int64_t ct_bytes = ncols_pad * t.kpad * (t.f32 ? 4 : 2);
+  if (ct_bytes >= (int64_t{1} << 31)) return 0;  // the column operand is addressed with 31-bit offsets
+  Carver c(nullptr);
+  c.take(static_cast<size_t>(ct_bytes));
+  c.take(static_cast<size_t>(batch) * t.n_dirs * sizeof(int16_t));
+  c.take(static_cast<size_t>(batch) * sizeof(int32_t));
+  c.take(static_cast<size_t>(batch) * sizeof(uint64_t));
+  return c.off;
+}
+
+hipError_t match_launch(const ScanTable& t, const uint8_t* free8, int W, int H, int pitch, int n_theta,
+                        const int16_t* zq_host, const int32_t* sz_host, int nq, void* ws, uint64_t* best_host,
+                        hipStream_t s) {
+  const int cells = H * pitch;
+  const int ncols = nq * n_theta, ncols_pad = round_up_i(ncols, 32);
+  const int tiles = (cells + kTileCells - 1) / kTileCells;
+  Carver c(ws);
+  void* ct = c.take(static_cast<size_t>(ncols_pad) * t.kpad * (t.f32 ? 4 : 2));
+  int16_t* zq = static_cast<int16_t*>(c.take(static_cast<size_t>(nq) * t.n_dirs * sizeof(int16_t)));
+  int32_t* sz = static_cast<int32_t*>(c.take(static_cast<size_t>(nq) * sizeof(int32_t)));
+  uint64_t* best = static_cast<uint64_t*>(c.take(static_cast<size_t>(nq) * sizeof(uint64_t)));
+  hipError_t e = hipMemcpyAsync(zq, zq_host, static_cast<size_t>(nq) * t.n_dirs * sizeof(int16_t),
+                                hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return e;
+  if ((e = hipMemcpyAsync(sz, sz_host, static_cast<size_t>(nq) * sizeof(int32_t), hipMemcpyHostToDevice, s)) !=
+      hipSuccess)
+    return e;
+  MatchCtArgs ca = {};
+  ca.ct = ct;
+  ca.zq = zq;
+  ca.n_dirs = t.n_dirs;
+  ca.n_theta = n_theta;
+  ca.ncols = ncols;
+  ca.ncols_pad = ncols_pad;
+  ca.kpad = t.kpad;
+  ca.f32 = t.f32 ? 1 : 0;
+  ca.best = best;
+  ca.nq = nq;
+  const double step = 2.0 * M_PI / t.n_dirs, dth = 2.0 * M_PI / n_theta;
+  for (int k = 0; k < n_theta; ++k) {
+    long v = static_cast<long>(floor((0.0 + k * dth) / step + 0.5)) % t.n_dirs;
+    if (v < 0) v += t.n_dirs;
+    ca.s[k] = static_cast<int16_t>(v);
+  }
+  const int64_t nct = static_cast<int64_t>(ncols_pad) * t.kpad;
+  hipLaunchKernelGGL(match_ct_kernel, dim3(static_cast<unsigned>((nct + 255) / 256)), dim3(256), 0, s, ca);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  MatchArgs a = {};
+  a.rq = t.rq;
+  a.sr = t.sr;
+  a.free8 = free8;
+  a.ct = ct;
+  a.sz = sz;
+  a.best = best;
+  a.cells = cells;
+  a.pitch = pitch;
+  a.W = W;
+  a.n_theta = n_theta;
+  a.ncols = ncols;
+  a.ncols_pad = ncols_pad;
+  a.kpad = t.kpad;
+  a.rq_bytes = static_cast<uint32_t>(t.rq_bytes);
+  // the A operand is held in registers for the whole table depth (at most 384)
+#define MCL_MATCH(KP)                                                                                   \
+  case KP:                                                                                              \
+    if (t.f32) hipLaunchKernelGGL((match_gemm_kernel<float, KP>), dim3(tiles), dim3(kScanThreads), 0, s, a); \
+    else hipLaunchKernelGGL((match_gemm_kernel<__bf16, KP>), dim3(tiles), dim3(kScanThreads), 0, s, a);      \
+    break;
+  switch (t.kpad) {
+    MCL_MATCH(64)
+    MCL_MATCH(128)
+    MCL_MATCH(192)
+    MCL_MATCH(256)
+    MCL_MATCH(320)
+    MCL_MATCH(384)
+    default: return hipErrorInvalidValue;
+  }
+#undef MCL_MATCH
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if ((e = hipMemcpyAsync(best_host, best, static_cast<size_t>(nq) * sizeof(uint64_t), hipMemcpyDeviceToHost, s)) !=
+      hipSuccess)
+    return e;
+  return hipStreamSynchronize(s);
 }
 
 int scan_tiles(int cells) { return (cells + kTileCells - 1) / kTileCells; }

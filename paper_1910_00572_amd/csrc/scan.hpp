@@ -53,6 +53,12 @@ hipError_t scan_launch(const ScanLaunch& L, const float* ranges_m, double sigma_
 // selected).  list and pos: H * pitch int32 each (sample list and positions).
 hipError_t scan_sampled_launch(const ScanLaunch& L, const float* ranges_m, double sigma_m, const uint8_t* mask,
                                int32_t* list, int32_t* pos);
+// Best match of nq quantised query scans over every free state (map
+// difficulty): synchronous; best_host[p] = (D << 39) | (k << 30) | dense cell.
+size_t match_workspace_bytes(const ScanTable& t, int cells, int n_theta, int batch);
+hipError_t match_launch(const ScanTable& t, const uint8_t* free8, int W, int H, int pitch, int n_theta,
+                        const int16_t* zq_host, const int32_t* sz_host, int nq, void* ws, uint64_t* best_host,
+                        hipStream_t s);
 size_t scan_work_bytes(int n_theta, int kpad);
 ScanWork scan_work_carve(void* base, int n_theta, int kpad);
 ScanTable scan_table_carve(Carver& c, const mcl_map_desc* d, int pitch, bool f32);

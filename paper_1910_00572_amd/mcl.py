@@ -29,7 +29,8 @@ ABI_SYMBOLS = [
     "mcl_filter_workspace_bytes", "mcl_init_belief", "mcl_filter_destroy", "mcl_step_odometry",
     "mcl_apply_scan", "mcl_normalize", "mcl_read_belief", "mcl_export_belief", "mcl_scan_sqdist",
     "mcl_get_info", "mcl_step_batch", "mcl_batch_workspace_bytes", "mcl_sample_cells",
-    "mcl_apply_scan_sampled", "mcl_dither",
+    "mcl_apply_scan_sampled", "mcl_dither", "mcl_match_workspace_bytes", "mcl_best_match",
+    "mcl_difficulty",
 ]
 
 
@@ -121,6 +122,13 @@ def load_library(path: str = _LIB_PATH):
     lib.mcl_apply_scan_sampled.argtypes = [c_void_p, c_void_p, c_int32, c_double, c_void_p]
     lib.mcl_dither.restype = c_int
     lib.mcl_dither.argtypes = [c_void_p, c_int32, c_int32, c_void_p, c_void_p]
+    lib.mcl_match_workspace_bytes.restype = c_size_t
+    lib.mcl_match_workspace_bytes.argtypes = [c_void_p, c_int32, c_int32]
+    lib.mcl_best_match.restype = c_int
+    lib.mcl_best_match.argtypes = [c_void_p, c_int32, c_void_p, c_int32, c_int32, c_void_p, c_void_p, c_void_p,
+                                   c_void_p, c_size_t, c_void_p]
+    lib.mcl_difficulty.restype = c_int
+    lib.mcl_difficulty.argtypes = [c_void_p, c_void_p, c_void_p, c_int32, c_double, c_void_p]
     _lib = lib
     return lib
 
@@ -323,6 +331,37 @@ def dither(intensity, out=None, stream=None):
     _check(load_library().mcl_dither(c_void_p(intensity.data_ptr()), int(W), int(H), c_void_p(out.data_ptr()),
                                      _stream_handle(stream)))
     return out
+
+
+def best_match(map: Map, n_theta, ranges_m, batch=64, stream=None):
+    """Best matching free state of each query scan (map difficulty): (cell j*W+i, heading, D) arrays."""
+    import torch
+    lib = load_library()
+    z = np.ascontiguousarray(ranges_m, dtype=np.float32)
+    n = z.shape[0]
+    nbytes = lib.mcl_match_workspace_bytes(map.handle, int(n_theta), int(batch))
+    if nbytes == 0:
+        raise MclError(ESTATE if map.n_dirs == 0 else EINVAL, "no workspace for these arguments")
+    ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    cell = np.empty(n, np.int32)
+    head = np.empty(n, np.int32)
+    dist = np.empty(n, np.int32)
+    _check(lib.mcl_best_match(map.handle, int(n_theta), z.ctypes.data, n, int(batch), cell.ctypes.data,
+                              head.ctypes.data, dist.ctypes.data, c_void_p(ws.data_ptr()), nbytes,
+                              _stream_handle(stream)))
+    return cell, head, dist
+
+
+def difficulty(map: Map, query_cells, best_cells, threshold_m=1.0):
+    """D_M: fraction of query cells whose best match lies more than threshold_m away."""
+    lib = load_library()
+    q = np.ascontiguousarray(query_cells, dtype=np.int32)
+    b = np.ascontiguousarray(best_cells, dtype=np.int32)
+    if q.shape != b.shape:
+        raise MclError(EINVAL, "query and best cell lists differ in length")
+    out = c_double()
+    _check(lib.mcl_difficulty(map.handle, q.ctypes.data, b.ctypes.data, len(q), float(threshold_m), byref(out)))
+    return out.value
 
 
 class BatchWorkspace:
