@@ -299,7 +299,7 @@ def bench_aniso(steps=100):
     return out
 
 
-def bench_match(grid=256, n_theta=72, batch=64):
+def bench_match(grid=256, n_theta=72, batch=256):
     """Map difficulty D_M on a grid x grid floor plan: the best match of a noisy
     scan (360 beams, sigma 0.1 m) taken at every free cell, over every free state."""
     import time

@@ -7,9 +7,10 @@
 // the 3-D blur is the theta blur followed by one rotated 2-D blur per
 // channel; the kernel activation G(B_0, k) of Alg. 1 depends on k too.
 //
+//   aniso_taps_kernel   each channel's rotated 2-D taps (FP64, normalised)
 //   aniso_theta_kernel  warp (Sec. III-A-1, bilinear or whole-cell), pre-blur
 //                       mask and circular theta blur -> FP32 scratch
-//   aniso_xy_kernel     per channel: rotated 2-D blur of the scratch and of
+//   aniso_xy_kernel     per channel (eight to a workgroup): rotated 2-D blur of the scratch and of
 //                       the free mask (the activation), post-blur mask and
 //                       M / G(B_0, k), store, sum/max; the last workgroup
 //                       renormalises as the fused step does
@@ -55,143 +56,228 @@ __device__ inline void channel_shift(const AnisoArgs& a, int k, int& nx, int& ny
   fy = static_cast<float>(dy - fdy);
 }
 
-// Grid (columns / kThThreads, H, n_theta): one output (k, j, i) per thread.
-// The shifts of the 2 rth + 1 source channels are computed once per workgroup.
+// Taps of every channel's rotated Gaussian, FP64, normalised to sum 1, stored
+// FP32 as taps[k][(n + r) d + m + r].  Grid n_theta, one workgroup per channel.
+__global__ __launch_bounds__(kThThreads) void aniso_taps_kernel(AnisoArgs a) {
+  __shared__ double tsum[kThThreads];
+  const int t = threadIdx.x, k = blockIdx.x;
+  const int r = a.rxy, d = 2 * r + 1;
+  double cs, sn;
+  sincos(a.noise_theta + k * a.dtheta, &sn, &cs);
+  double w[1 + (2 * kAnisoMaxRadius + 1) * (2 * kAnisoMaxRadius + 1) / kThThreads];
+  double part = 0.0;
+  int u = 0;
+  for (int e = t; e < d * d; e += kThThreads, ++u) {
+    const int n = e / d - r, m = e % d - r;
+    const double al = cs * m + sn * n, ac = -sn * m + cs * n;
+    const double q = al * al / (a.sf * a.sf) + ac * ac / (a.sl * a.sl);
+    w[u] = exp(-0.5 * q);
+    part += w[u];
+  }
+  tsum[t] = part;
+  __syncthreads();
+  for (int st = kThThreads / 2; st > 0; st >>= 1) {
+    if (t < st) tsum[t] += tsum[t + st];
+    __syncthreads();
+  }
+  const double z = tsum[0];
+  u = 0;
+  for (int e = t; e < d * d; e += kThThreads, ++u) a.taps[k * d * d + e] = static_cast<float>(w[u] / z);
+}
+
+// Warp, pre-blur mask and circular theta blur into the FP32 scratch.  Grid
+// (pitch / kThThreads, H): one cell per thread, streaming through the
+// channels.  Each channel's warped value is computed once and kept in a
+// shift register of the last 2 rth + 1 channels; output channel k is emitted
+// when channel k + rth has arrived.  The next channel's four source values
+// are loaded before the current one is combined.
 template <typename T>
 __global__ __launch_bounds__(kThThreads) void aniso_theta_kernel(AnisoArgs a) {
-  __shared__ int snx[kMaxTaps], sny[kMaxTaps];
-  __shared__ float sfx[kMaxTaps], sfy[kMaxTaps];
+  __shared__ int snx[kMaxTheta], sny[kMaxTheta];
+  __shared__ float sfx[kMaxTheta], sfy[kMaxTheta];
   const int t = threadIdx.x;
   const int i = blockIdx.x * kThThreads + t;
-  const int j = blockIdx.y, k = blockIdx.z;
-  const int nl = 2 * a.rth + 1;
-  if (t < nl) {
-    int ks = (k - (t - a.rth)) % a.n_theta;
-    if (ks < 0) ks += a.n_theta;
-    channel_shift(a, ks, snx[t], sny[t], sfx[t], sfy[t]);
-  }
+  const int j = blockIdx.y;
+  const int n = a.n_theta, rth = a.rth, nt = 2 * a.rth + 1;
+  for (int k = t; k < n; k += kThThreads) channel_shift(a, k, snx[k], sny[k], sfx[k], sfy[k]);
   __syncthreads();
   if (i >= a.pitch) return;
   const FilterDev* dev = a.dev;
   const T* __restrict__ bin = static_cast<const T*>(a.buf[dev->cur]);
   const float scale = dev->scale;
-  float acc = 0.f;
-  if (i < a.W) {
-    for (int l = 0; l < nl; ++l) {
-      int ks = (k - (l - a.rth)) % a.n_theta;
-      if (ks < 0) ks += a.n_theta;
-      const int nx = snx[l], ny = sny[l];
-      const float fx = sfx[l], fy = sfy[l];
-      const T* plane = bin + static_cast<int64_t>(ks) * a.sstride;
-      float s = 0.f;
+  const bool inside = i < a.W;
+  const float mp = inside ? a.mpre[static_cast<int64_t>(j) * a.pitch + i] * scale : 0.f;
+  float* __restrict__ out = a.tmp + static_cast<int64_t>(j) * a.pitch + i;
+  // the four source values of channel c (zero outside the grid) and their weights
+  auto fetch = [&](int c, float v[4]) {
+    const int nx = snx[c], ny = sny[c];
+    const T* plane = bin + static_cast<int64_t>(c) * a.sstride;
 #pragma unroll
-      for (int b = 0; b < 2; ++b) {
-        const int jj = j - ny - b;
-        const float wy = b ? fy : 1.f - fy;
+    for (int b = 0; b < 2; ++b) {
+      const int jj = j - ny - b;
+      const bool oky = jj >= 0 && jj < a.H;
+      const int jc = min(max(jj, 0), a.H - 1);
 #pragma unroll
-        for (int c = 0; c < 2; ++c) {
-          const int ii = i - nx - c;
-          const float wx = c ? fx : 1.f - fx;
-          if (jj >= 0 && jj < a.H && ii >= 0 && ii < a.W)
-            s += (wx * wy) * ld<T>(plane + static_cast<int64_t>(jj) * a.pitch + ii);
-        }
+      for (int q = 0; q < 2; ++q) {
+        const int ii = i - nx - q;
+        const bool ok = oky && ii >= 0 && ii < a.W;
+        const int ic = min(max(ii, 0), a.W - 1);
+        const float x = ld<T>(plane + static_cast<int64_t>(jc) * a.pitch + ic);
+        v[2 * b + q] = ok ? x : 0.f;
       }
-      acc += a.gth[l] * (s * scale);
     }
-    acc *= a.mpre[static_cast<int64_t>(j) * a.pitch + i];
+  };
+  float ring[kMaxTaps];
+#pragma unroll
+  for (int l = 0; l < kMaxTaps; ++l) ring[l] = 0.f;
+  const int total = n + 2 * rth;  // channels -rth .. n - 1 + rth
+  int c = (n - rth % n) % n;
+  float v[4];
+  fetch(c, v);
+  for (int e = 0; e < total; ++e) {
+    const float fx = sfx[c], fy = sfy[c];
+    const int cn = c + 1 == n ? 0 : c + 1;
+    float vn[4];
+    if (e + 1 < total) fetch(cn, vn);
+    const float s = ((1.f - fx) * v[0] + fx * v[1]) * (1.f - fy) + ((1.f - fx) * v[2] + fx * v[3]) * fy;
+#pragma unroll
+    for (int l = kMaxTaps - 1; l > 0; --l) ring[l] = ring[l - 1];
+    ring[0] = inside ? s * mp : 0.f;
+    if (e >= 2 * rth) {
+      // ring[l] holds channel (k + rth - l): output k = e - 2 rth
+      float acc = 0.f;
+#pragma unroll
+      for (int l = 0; l < kMaxTaps; ++l) acc += (l < nt ? a.gth[l] : 0.f) * ring[l];
+      out[static_cast<int64_t>(e - 2 * rth) * a.sstride] = acc;
+    }
+    c = cn;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) v[q] = vn[q];
   }
-  a.tmp[static_cast<int64_t>(k) * a.sstride + static_cast<int64_t>(j) * a.pitch + i] = acc;
 }
 
 constexpr int kXyTx = 64, kXyTy = 16, kXyThreads = 256;
+constexpr int kXyRows = kXyTy / (kXyThreads / kXyTx);  // outputs per thread, down a column
+constexpr int kXyChannels = 8;                          // channels per workgroup
 
 template <typename T>
 __device__ inline T store_t(float v) {
   return static_cast<T>(v);
 }
 
-// Grid (tiles_x, tiles_y, n_theta): one 64 x 16 output tile of one channel.
-template <typename T>
+// Grid (tiles_x, tiles_y, channel groups): one 64 x 16 output tile for up to
+// kXyChannels consecutive channels.  The free-mask tile is loaded once; the
+// scratch tile of the next channel is loaded into registers while the current
+// one is blurred from LDS (double buffered, one barrier per channel).  Each
+// thread computes a column of four outputs, so a row it reads from LDS serves
+// up to four of them.  One sum/max reduction per workgroup.
+template <typename T, int R>
 __global__ __launch_bounds__(kXyThreads) void aniso_xy_kernel(AnisoArgs a) {
-  constexpr int MAXD = 2 * kAnisoMaxRadius + 1;
-  constexpr int LW = kXyTx + 2 * kAnisoMaxRadius, LH = kXyTy + 2 * kAnisoMaxRadius;
-  __shared__ float ts[LH * LW];
-  __shared__ float ms[LH * LW];
-  __shared__ float taps[MAXD * MAXD];
-  __shared__ double tsum[kXyThreads];
+  constexpr int D = 2 * R + 1;
+  constexpr int LW = kXyTx + 2 * R, LH = kXyTy + 2 * R, NL = LW * LH;
+  constexpr int PER = (NL + kXyThreads - 1) / kXyThreads;
+  __shared__ float ts[2][NL];
+  __shared__ float ms[NL];
+  __shared__ float gs[2][D * D];
   __shared__ double red_s[kXyThreads];
   __shared__ float red_m[kXyThreads];
   __shared__ int last_flag;
   const int t = threadIdx.x;
-  const int r = a.rxy, d = 2 * r + 1;
-  const int lw = kXyTx + 2 * r, lh = kXyTy + 2 * r;
-  const int k = blockIdx.z;
+  const int k0 = blockIdx.z * kXyChannels;
+  const int k1 = min(a.n_theta, k0 + kXyChannels);
   const int x0 = blockIdx.x * kXyTx, y0 = blockIdx.y * kXyTy;
   FilterDev* dev = a.dev;
   const int cur = dev->cur;
   const float scale = dev->scale;
   T* __restrict__ bout = static_cast<T*>(a.buf[cur ^ 1]);
 
-  // taps of this channel's rotated Gaussian, FP64, normalised to sum 1
-  double cs, sn;
-  sincos(a.noise_theta + k * a.dtheta, &sn, &cs);
-  double w = 0.0;
-  for (int e = t; e < d * d; e += kXyThreads) {
-    const int n = e / d - r, m = e % d - r;
-    const double al = cs * m + sn * n, ac = -sn * m + cs * n;
-    const double q = al * al / (a.sf * a.sf) + ac * ac / (a.sl * a.sl);
-    w += exp(-0.5 * q);
+  // this thread's share of the halo tile: grid offsets (or -1 outside the grid)
+  int64_t off[PER];
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int e = t + u * kXyThreads;
+    const int ly = e / LW, lx = e - ly * LW;
+    const int gy = y0 + ly - R, gx = x0 + lx - R;
+    const bool in = e < NL && gy >= 0 && gy < a.H && gx >= 0 && gx < a.W;
+    off[u] = in ? static_cast<int64_t>(gy) * a.pitch + gx : -1;
   }
-  tsum[t] = w;
-  // scratch and free-mask tiles with a halo of r cells (zero outside the grid)
-  const float* __restrict__ src = a.tmp + static_cast<int64_t>(k) * a.sstride;
-  for (int e = t; e < lw * lh; e += kXyThreads) {
-    const int ly = e / lw, lx = e % lw;
-    const int gy = y0 + ly - r, gx = x0 + lx - r;
-    const bool in = gy >= 0 && gy < a.H && gx >= 0 && gx < a.W;
-    const int64_t o = static_cast<int64_t>(gy) * a.pitch + gx;
-    ts[ly * LW + lx] = in ? src[o] : 0.f;
-    ms[ly * LW + lx] = in ? static_cast<float>(a.free8[o]) : 0.f;
+  // loads from a clamped (valid) address, then a select: no branches around them
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const float v = static_cast<float>(a.free8[off[u] >= 0 ? off[u] : 0]);
+    if (t + u * kXyThreads < NL) ms[t + u * kXyThreads] = off[u] >= 0 ? v : 0.f;
   }
-  __syncthreads();
-  for (int st = kXyThreads / 2; st > 0; st >>= 1) {
-    if (t < st) tsum[t] += tsum[t + st];
-    __syncthreads();
-  }
-  const double z = tsum[0];
-  for (int e = t; e < d * d; e += kXyThreads) {
-    const int n = e / d - r, m = e % d - r;
-    const double al = cs * m + sn * n, ac = -sn * m + cs * n;
-    const double q = al * al / (a.sf * a.sf) + ac * ac / (a.sl * a.sl);
-    taps[e] = static_cast<float>(exp(-0.5 * q) / z);
-  }
-  __syncthreads();
+  // the next channel's scratch tile and taps, held in registers until stored
+  float pre[PER];
+  float tap = 0.f;
+  auto fetch = [&](int k) {
+    const float* __restrict__ src = a.tmp + static_cast<int64_t>(k) * a.sstride;
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const float v = src[off[u] >= 0 ? off[u] : 0];
+      pre[u] = off[u] >= 0 ? v : 0.f;
+    }
+    tap = a.taps[k * D * D + (t < D * D ? t : 0)];
+  };
+  auto put = [&](int b) {
+#pragma unroll
+    for (int u = 0; u < PER; ++u)
+      if (t + u * kXyThreads < NL) ts[b][t + u * kXyThreads] = pre[u];
+    if (t < D * D) gs[b][t] = tap;
+  };
+  fetch(k0);
+  put(0);
 
-  // four outputs per thread: out(i, j) = sum_{m, n} g[n][m] s(i - m, j - n)
+  const int ox = t % kXyTx, oy0 = (t / kXyTx) * kXyRows;
   double s = 0.0;
   float mx = 0.f;
-  for (int o = t; o < kXyTx * kXyTy; o += kXyThreads) {
-    const int oy = o / kXyTx, ox = o % kXyTx;
-    const int gy = y0 + oy, gx = x0 + ox;
-    if (gy >= a.H || gx >= a.W) continue;
-    float tv = 0.f, av = 0.f;
-    for (int n = -r; n <= r; ++n) {
-      const float* trow = ts + (oy + r - n) * LW + (ox + r);
-      const float* mrow = ms + (oy + r - n) * LW + (ox + r);
-      const float* g = taps + (n + r) * d + r;
-      for (int m = -r; m <= r; ++m) {
-        tv += g[m] * trow[-m];
-        av += g[m] * mrow[-m];
+  for (int k = k0; k < k1; ++k) {
+    const int b = (k - k0) & 1;
+    __syncthreads();
+    if (k + 1 < k1) fetch(k + 1);
+    // out(i, j) = sum_{m, n} g[n][m] s(i - m, j - n): LDS row ly holds j - n + R,
+    // column lx holds i - m + R
+    const float* g = gs[b];
+    float tv[kXyRows], av[kXyRows];
+#pragma unroll
+    for (int q = 0; q < kXyRows; ++q) tv[q] = av[q] = 0.f;
+    // one tap column at a time (not unrolled), so only 2R + 1 taps and one
+    // column of LDS values are live
+#pragma unroll 1
+    for (int m = -R; m <= R; ++m) {
+      float gc[D];
+#pragma unroll
+      for (int n = 0; n < D; ++n) gc[n] = g[n * D + m + R];
+      const float* tcol = ts[b] + oy0 * LW + ox + R - m;
+      const float* mcol = ms + oy0 * LW + ox + R - m;
+#pragma unroll
+      for (int dy = 0; dy < kXyRows + 2 * R; ++dy) {
+        const float vt = tcol[dy * LW], vm = mcol[dy * LW];
+#pragma unroll
+        for (int q = 0; q < kXyRows; ++q) {
+          const int nn = q + R - dy;  // row offset n of this input for output q
+          if (nn >= -R && nn <= R) {
+            tv[q] += gc[nn + R] * vt;
+            av[q] += gc[nn + R] * vm;
+          }
+        }
       }
     }
-    const bool free = ms[(oy + r) * LW + ox + r] > 0.f;
-    float u = 0.f;
-    if (free) u = a.wall_normalize ? tv / (av * a.gth_sum) : tv;
-    const T q = store_t<T>(u);
-    bout[static_cast<int64_t>(k) * a.sstride + static_cast<int64_t>(gy) * a.pitch + gx] = q;
-    const float uq = static_cast<float>(q);
-    s += static_cast<double>(uq);
-    mx = fmaxf(mx, uq);
+#pragma unroll
+    for (int q = 0; q < kXyRows; ++q) {
+      const int gy = y0 + oy0 + q, gx = x0 + ox;
+      if (gy < a.H && gx < a.W) {
+        const bool free = ms[(oy0 + q + R) * LW + ox + R] > 0.f;
+        float u = 0.f;
+        if (free) u = a.wall_normalize ? tv[q] / (av[q] * a.gth_sum) : tv[q];
+        const T qv = store_t<T>(u);
+        bout[static_cast<int64_t>(k) * a.sstride + static_cast<int64_t>(gy) * a.pitch + gx] = qv;
+        const float uq = static_cast<float>(qv);
+        s += static_cast<double>(uq);
+        mx = fmaxf(mx, uq);
+      }
+    }
+    if (k + 1 < k1) put(b ^ 1);
   }
   red_s[t] = s;
   red_m[t] = mx;
@@ -247,32 +333,40 @@ __global__ __launch_bounds__(kXyThreads) void aniso_xy_kernel(AnisoArgs a) {
   }
 }
 
-}  // namespace
-
-int aniso_workgroups(int W, int H, int n_theta) {
-  return ((W + kXyTx - 1) / kXyTx) * ((H + kXyTy - 1) / kXyTy) * n_theta;
-}
-
-hipError_t launch_aniso_step(int dtype, const AnisoArgs& a, hipStream_t s) {
-  if (a.rxy < 0 || a.rxy > kAnisoMaxRadius || a.rth < 0 || a.rth > kMaxRadius) return hipErrorInvalidValue;
-  const dim3 g1((a.pitch + kThThreads - 1) / kThThreads, a.H, a.n_theta);
-  const dim3 g2((a.W + kXyTx - 1) / kXyTx, (a.H + kXyTy - 1) / kXyTy, a.n_theta);
-  switch (dtype) {
-    case 0:
-      hipLaunchKernelGGL(aniso_theta_kernel<float>, g1, dim3(kThThreads), 0, s, a);
-      hipLaunchKernelGGL(aniso_xy_kernel<float>, g2, dim3(kXyThreads), 0, s, a);
-      break;
-    case 1:
-      hipLaunchKernelGGL(aniso_theta_kernel<__bf16>, g1, dim3(kThThreads), 0, s, a);
-      hipLaunchKernelGGL(aniso_xy_kernel<__bf16>, g2, dim3(kXyThreads), 0, s, a);
-      break;
-    case 2:
-      hipLaunchKernelGGL(aniso_theta_kernel<_Float16>, g1, dim3(kThThreads), 0, s, a);
-      hipLaunchKernelGGL(aniso_xy_kernel<_Float16>, g2, dim3(kXyThreads), 0, s, a);
-      break;
+template <typename T>
+hipError_t launch_typed(const AnisoArgs& a, hipStream_t s) {
+  const dim3 g1((a.pitch + kThThreads - 1) / kThThreads, a.H);
+  const dim3 g2((a.W + kXyTx - 1) / kXyTx, (a.H + kXyTy - 1) / kXyTy, (a.n_theta + kXyChannels - 1) / kXyChannels);
+  hipLaunchKernelGGL(aniso_taps_kernel, dim3(a.n_theta), dim3(kThThreads), 0, s, a);
+  hipLaunchKernelGGL(aniso_theta_kernel<T>, g1, dim3(kThThreads), 0, s, a);
+  switch (a.rxy) {
+    case 0: hipLaunchKernelGGL((aniso_xy_kernel<T, 0>), g2, dim3(kXyThreads), 0, s, a); break;
+    case 1: hipLaunchKernelGGL((aniso_xy_kernel<T, 1>), g2, dim3(kXyThreads), 0, s, a); break;
+    case 2: hipLaunchKernelGGL((aniso_xy_kernel<T, 2>), g2, dim3(kXyThreads), 0, s, a); break;
+    case 3: hipLaunchKernelGGL((aniso_xy_kernel<T, 3>), g2, dim3(kXyThreads), 0, s, a); break;
+    case 4: hipLaunchKernelGGL((aniso_xy_kernel<T, 4>), g2, dim3(kXyThreads), 0, s, a); break;
+    case 5: hipLaunchKernelGGL((aniso_xy_kernel<T, 5>), g2, dim3(kXyThreads), 0, s, a); break;
+    case 6: hipLaunchKernelGGL((aniso_xy_kernel<T, 6>), g2, dim3(kXyThreads), 0, s, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+}  // namespace
+
+int aniso_workgroups(int W, int H, int n_theta) {
+  return ((W + kXyTx - 1) / kXyTx) * ((H + kXyTy - 1) / kXyTy) * ((n_theta + kXyChannels - 1) / kXyChannels);
+}
+
+hipError_t launch_aniso_step(int dtype, const AnisoArgs& a, hipStream_t s) {
+  static_assert(kAnisoMaxRadius == 6, "instantiate aniso_xy_kernel for every radius");
+  if (a.rxy < 0 || a.rxy > kAnisoMaxRadius || a.rth < 0 || a.rth > kMaxRadius || !a.taps) return hipErrorInvalidValue;
+  switch (dtype) {
+    case 0: return launch_typed<float>(a, s);
+    case 1: return launch_typed<__bf16>(a, s);
+    case 2: return launch_typed<_Float16>(a, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 }  // namespace mcl

@@ -164,6 +164,7 @@ struct mcl_filter_s {
   double rem[kMaxTheta][2] = {};  // carried remainders of the whole-cell warp, cells
   int32_t* ishift = nullptr;      // device: whole-cell shifts of the current warp
   float* aniso_tmp = nullptr;     // MCL_ANISOTROPIC: FP32 scratch of the theta-blurred tensor
+  float* aniso_taps = nullptr;    // MCL_ANISOTROPIC: FP32 2-D taps per channel
   double sf = 0.0, sl = 0.0;      // MCL_ANISOTROPIC: std-devs along / across the heading
   int raniso = 0;                 // MCL_ANISOTROPIC: 2-D kernel radius
   double gth_sum = 1.0;           // sum of the theta taps
@@ -309,6 +310,10 @@ size_t carve_filter(mcl_filter f, void* ws, const mcl_map m, const mcl_params* p
   FilterDev* dev = static_cast<FilterDev*>(c.take(kDevRegionBytes));
   int32_t* ishift = static_cast<int32_t*>(c.take(2 * kMaxTheta * sizeof(int32_t)));
   float* atmp = (p->flags & MCL_ANISOTROPIC) ? static_cast<float*>(c.take(n * sizeof(float))) : nullptr;
+  constexpr int kAnisoTaps = (2 * kAnisoMaxRadius + 1) * (2 * kAnisoMaxRadius + 1);
+  float* ataps = (p->flags & MCL_ANISOTROPIC)
+                     ? static_cast<float*>(c.take(static_cast<size_t>(p->n_theta) * kAnisoTaps * sizeof(float)))
+                     : nullptr;
   float* scratch = nullptr;
   int32_t* samp = nullptr;
   if (m->scan.n_dirs > 0) {
@@ -327,6 +332,7 @@ size_t carve_filter(mcl_filter f, void* ws, const mcl_map m, const mcl_params* p
     f->samp_list = samp;
     f->ishift = ishift;
     f->aniso_tmp = atmp;
+    f->aniso_taps = ataps;
     f->scanw = scan_work_carve(scanw, p->n_theta, m->scan.kpad);
     f->sstride = sstride;
     f->shape = sh;
@@ -571,6 +577,7 @@ static AnisoArgs make_aniso_args(mcl_filter f, const StepArgs& s, double theta_p
   a.buf[0] = f->buf[0];
   a.buf[1] = f->buf[1];
   a.tmp = f->aniso_tmp;
+  a.taps = f->aniso_taps;
   a.mpre = m->mpre;
   a.free8 = m->free8;
   a.partials = f->partials;

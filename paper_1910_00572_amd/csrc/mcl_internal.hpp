@@ -92,6 +92,7 @@ constexpr int kAnisoMaxRadius = 6;  // 2-D kernel radius, cells
 struct AnisoArgs {
   void* buf[2];
   float* tmp;                 // FP32 scratch, [k][j][pitch]
+  float* taps;                // FP32 2-D taps, [k][(2 rxy + 1)^2], written by the first kernel
   const float* mpre;          // pre-blur traversability, [j][pitch]
   const uint8_t* free8;       // free cells, [j][pitch] (0 outside the grid)
   double* partials;           // 2 doubles per workgroup of the second pass

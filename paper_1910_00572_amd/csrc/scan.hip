@@ -836,7 +836,7 @@ struct MatchArgs {
   const void* rq;          // MFMA-tiled range table
   const int32_t* sr;       // [cells] sum of squares
   const uint8_t* free8;    // [cells] free cells (pitch layout; 0 outside the grid)
-  const void* ct;          // [ncols_pad][kpad] circulant columns, column = query * n_theta + k
+  const void* ct;          // circulant columns (column = query * n_theta + k), MFMA-tiled per 32 columns
   const int32_t* sz;       // [batch] sum of squared counts of each query
   uint64_t* best;          // [batch], all ones before the launch
   int32_t cells, pitch, W, n_theta, ncols, ncols_pad, kpad;
@@ -845,13 +845,25 @@ struct MatchArgs {
 
 constexpr uint64_t kNoKey = ~0ull;
 
+// One workgroup: 128 cells (32 per wave, A operand in registers for the whole
+// depth) against every column block of the batch.  A block of 32 columns is
+// loaded once per workgroup into LDS, double buffered, in the order the MFMA
+// reads it ([depth step][lane]), so all four waves share it.  Within the
+// workgroup a candidate is a 32-bit key (D << 7 | local cell); D < 2^25 for
+// any table of at most 384 directions, so the key is exact.  Per block, one
+// wave in turn widens the per-column minima to (D, k, dense cell) keys and
+// folds them per query into best[] with a 64-bit atomic min.
 template <typename OP, int KPAD>
 __global__ __launch_bounds__(kScanThreads) void match_gemm_kernel(MatchArgs a) {
-  __shared__ uint64_t wmin[kScanThreads / 64][32];
   constexpr int KSTEP = Mfma<OP>::KSTEP, HALF = Mfma<OP>::HALF, EB = sizeof(OP);
   constexpr int KS = KPAD / KSTEP;
-  constexpr int PB = 8;  // B operand prefetch depth
+  constexpr int BLK = KS * 64;                // 16-byte pieces in one 32-column block
+  constexpr int PER = BLK / kScanThreads;     // pieces each thread stages per block
+  constexpr int PB = 4;                       // LDS read-ahead in depth steps
+  static_assert(BLK % kScanThreads == 0, "block not divisible among the threads");
   using Vec = typename Mfma<OP>::Vec;
+  __shared__ Vec bs[2][BLK];
+  __shared__ uint32_t wmin[2][kScanThreads / 64][32];
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
   const int half = lane >> 5, col = lane & 31;
   const int cell0 = blockIdx.x * kTileCells + wv * 32;
@@ -861,69 +873,89 @@ __global__ __launch_bounds__(kScanThreads) void match_gemm_kernel(MatchArgs a) {
       const_cast<void*>(a.rq), static_cast<short>(0), static_cast<int>(a.rq_bytes), 0x00020000);
   const __amdgpu_buffer_rsrc_t rb = __builtin_amdgcn_make_buffer_rsrc(
       const_cast<void*>(a.ct), static_cast<short>(0), static_cast<int>(a.ncols_pad * a.kpad * EB), 0x00020000);
+  const int ncb = a.ncols_pad / 32;
+  // stage column block 0
+  {
+    Vec v[PER];
+#pragma unroll
+    for (int u = 0; u < PER; ++u)
+      v[u] = __builtin_bit_cast(Vec, __builtin_amdgcn_raw_buffer_load_b128(rb, static_cast<uint32_t>((t + u * kScanThreads) * 16), 0, 0));
+#pragma unroll
+    for (int u = 0; u < PER; ++u) bs[0][t + u * kScanThreads] = v[u];
+  }
   // this wave's 32 cells: the A operand stays in registers for every column
   Vec av[KS];
   const uint32_t va = static_cast<uint32_t>(((cell0 >> 5) * 64 + lane) * HALF * EB);
 #pragma unroll
   for (int st = 0; st < KS; ++st)
     av[st] = __builtin_bit_cast(Vec, __builtin_amdgcn_raw_buffer_load_b128(ra, va, static_cast<uint32_t>(st) * astep_bytes, 0));
-  // the lane's 16 accumulator rows: sum of squares and the candidate part of the key
-  int srow[16];
-  uint64_t qrow[16];  // dense cell index, or kNoKey for cells that are not candidates
+  // the lane's 16 accumulator rows: (Sr << 7 | local cell) and whether the cell is a candidate
+  uint32_t rbase[16];
+  uint32_t okmask = 0;
 #pragma unroll
   for (int g = 0; g < 4; ++g) {
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const int cell = cell0 + 8 * g + 4 * half + i;
-      const int j = cell / a.pitch, x = cell - j * a.pitch;
+      const int lc = wv * 32 + 8 * g + 4 * half + i;
+      const int cell = blockIdx.x * kTileCells + lc;
+      const int x = cell % a.pitch;
       const bool ok = cell < a.cells && x < a.W && a.free8[min(cell, a.cells - 1)] != 0;
-      srow[4 * g + i] = a.sr[min(cell, a.cells - 1)];
-      qrow[4 * g + i] = ok ? static_cast<uint64_t>(j) * a.W + x : kNoKey;
+      rbase[4 * g + i] = (static_cast<uint32_t>(a.sr[min(cell, a.cells - 1)]) << 7) | static_cast<uint32_t>(lc);
+      okmask |= ok ? (1u << (4 * g + i)) : 0u;
     }
   }
-  for (int cb = 0; cb < a.ncols_pad / 32; ++cb) {
-    const uint32_t vb = static_cast<uint32_t>(((cb * 32 + col) * a.kpad + HALF * half) * EB);
-    Vec bbuf[PB];
+  __syncthreads();
+  for (int cb = 0; cb < ncb; ++cb) {
+    // prefetch the next block into registers (past the end the loads return zeros)
+    Vec nx[PER];
 #pragma unroll
-    for (int u = 0; u < PB; ++u)
-      bbuf[u] = __builtin_bit_cast(Vec, __builtin_amdgcn_raw_buffer_load_b128(rb, vb, static_cast<uint32_t>(u * KSTEP * EB), 0));
+    for (int u = 0; u < PER; ++u)
+      nx[u] = __builtin_bit_cast(Vec, __builtin_amdgcn_raw_buffer_load_b128(
+                  rb, static_cast<uint32_t>(((cb + 1) * BLK + t + u * kScanThreads) * 16), 0, 0));
+    const Vec* B = bs[cb & 1];
+    Vec bf[PB];
+#pragma unroll
+    for (int u = 0; u < PB; ++u) bf[u] = B[u * 64 + lane];
     f32x16 acc;
 #pragma unroll
     for (int i = 0; i < 16; ++i) acc[i] = 0.f;
 #pragma unroll
     for (int st = 0; st < KS; ++st) {
-      Mfma<OP>::mma(av[st], bbuf[st % PB], acc);
-      __builtin_amdgcn_sched_barrier(0);
-      if (st + PB < KS)
-        bbuf[st % PB] = __builtin_bit_cast(
-            Vec, __builtin_amdgcn_raw_buffer_load_b128(rb, vb, static_cast<uint32_t>((st + PB) * KSTEP * EB), 0));
-      __builtin_amdgcn_sched_barrier(0);
+      Mfma<OP>::mma(av[st], bf[st % PB], acc);
+      if (st + PB < KS) bf[st % PB] = B[(st + PB) * 64 + lane];
     }
-    // column of this lane: query p, heading k
+    // column of this lane; key = (Sz + Sr - 2X) << 7 | local cell, exact in 32 bits
     const int c = cb * 32 + col;
-    const bool cval = c < a.ncols;
-    const int p = cval ? c / a.n_theta : 0, k = cval ? c - p * a.n_theta : 0;
-    const int szp = a.sz[p];
-    uint64_t m = kNoKey;
+    const int p = c < a.ncols ? c / a.n_theta : 0;
+    const uint32_t sz7 = static_cast<uint32_t>(a.sz[p]) << 7;
+    uint32_t m = ~0u;
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
-      const uint64_t d = static_cast<uint64_t>(szp - 2 * static_cast<int>(acc[r]) + srow[r]);
-      const uint64_t key = (qrow[r] == kNoKey || !cval) ? kNoKey : (d << 39) | (static_cast<uint64_t>(k) << 30) | qrow[r];
-      m = key < m ? key : m;
+      const uint32_t key = rbase[r] + sz7 - (static_cast<uint32_t>(static_cast<int>(acc[r])) << 8);
+      m = ((okmask >> r) & 1u) && key < m ? key : m;
     }
-    const uint64_t o = __shfl_xor(m, 32);  // the other 16 rows of the same column
+    const uint32_t o = __shfl_xor(m, 32);  // the other 16 rows of the same column
     m = o < m ? o : m;
-    if (half == 0) wmin[wv][col] = m;
+    if (half == 0) wmin[cb & 1][wv][col] = m;
+#pragma unroll
+    for (int u = 0; u < PER; ++u) bs[(cb + 1) & 1][t + u * kScanThreads] = nx[u];
     __syncthreads();
-    if (wv == 0) {
+    if (wv == (cb & 3)) {
       // lanes 0..31: one column each; the columns of one query are contiguous
       const int cc = cb * 32 + lane;
       uint64_t b = kNoKey;
       int q = -1;
       if (lane < 32 && cc < a.ncols) {
-        b = wmin[0][lane];
-        for (int w = 1; w < kScanThreads / 64; ++w) b = wmin[w][lane] < b ? wmin[w][lane] : b;
+        uint32_t w = wmin[cb & 1][0][lane];
+#pragma unroll
+        for (int v = 1; v < kScanThreads / 64; ++v) w = wmin[cb & 1][v][lane] < w ? wmin[cb & 1][v][lane] : w;
         q = cc / a.n_theta;
+        if (w != ~0u) {
+          const int cell = blockIdx.x * kTileCells + static_cast<int>(w & 127u);
+          const int j = cell / a.pitch, x = cell - j * a.pitch;
+          const uint64_t k = static_cast<uint64_t>(cc - q * a.n_theta);
+          b = (static_cast<uint64_t>(w >> 7) << 39) | (k << 30) | (static_cast<uint64_t>(j) * a.W + x);
+        }
       }
       // segmented suffix minimum: lane t ends with the minimum of its query's lanes from t on
 #pragma unroll
@@ -936,11 +968,11 @@ __global__ __launch_bounds__(kScanThreads) void match_gemm_kernel(MatchArgs a) {
       if (q >= 0 && (lane == 0 || pq != q) && b != kNoKey)
         __hip_atomic_fetch_min(a.best + q, b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    __syncthreads();
   }
 }
 
-// Circulant columns of a batch of queries: C[p * n_theta + k][beta] = zq_p[(beta - s_k) mod N].
+// Circulant columns of a batch of queries: C[p * n_theta + k][beta] = zq_p[(beta - s_k) mod N],
+// stored in the order the product kernel stages them.
 struct MatchCtArgs {
   void* ct;
   const int16_t* zq;        // [batch][n_dirs]
@@ -954,6 +986,12 @@ __global__ void match_ct_kernel(MatchCtArgs a) {
   if (idx < a.nq) a.best[idx] = kNoKey;
   if (idx >= static_cast<int64_t>(a.ncols_pad) * a.kpad) return;
   const int c = static_cast<int>(idx / a.kpad), beta = static_cast<int>(idx % a.kpad);
+  // MFMA-tiled: per 32-column block, [depth step][lane half][column][HALF]
+  const int kstep = a.f32 ? Mfma<float>::KSTEP : Mfma<__bf16>::KSTEP;
+  const int hf = a.f32 ? Mfma<float>::HALF : Mfma<__bf16>::HALF;
+  const int st = beta / kstep, within = beta - st * kstep;
+  const int64_t dst = ((static_cast<int64_t>(c / 32) * (a.kpad / kstep) + st) * 64 + (within / hf) * 32 + (c & 31)) * hf +
+                      within % hf;
   float v = 0.f;
   if (c < a.ncols && beta < a.n_dirs) {
     const int p = c / a.n_theta, k = c - p * a.n_theta;
@@ -962,9 +1000,9 @@ __global__ void match_ct_kernel(MatchCtArgs a) {
     v = static_cast<float>(a.zq[static_cast<int64_t>(p) * a.n_dirs + b]);
   }
   if (a.f32)
-    static_cast<float*>(a.ct)[idx] = v;
+    static_cast<float*>(a.ct)[dst] = v;
   else
-    static_cast<__bf16*>(a.ct)[idx] = static_cast<__bf16>(v);
+    static_cast<__bf16*>(a.ct)[dst] = static_cast<__bf16>(v);
 }
 
 // ---- map table: quantise ranges ---------------------------------------------------------

@@ -85,6 +85,8 @@ def test_every_kernel_shape(shape, monkeypatch):
     ((48, 41), 10, 0.9, 0.5, 0.7, -1, 3 | 16 | 32),
     ((40, 33), 6, 1.5, 0.6, 0.9, -1, 3 | 4 | 32),
     ((90, 70), 36, 1.1, 0.5, 1.0, -1, 3 | 32),
+    ((30, 25), 2, 2.0, 0.7, 1.0, -1, 3 | 32),  # radius 6; theta radius 3 wraps two channels
+    ((33, 21), 5, 0.4, 0.3, 0.5, 1, 3 | 32),   # radius 1
 ])
 def test_anisotropic_noise(case):
     # heading-rotated anisotropic noise (two-pass kernels) against the oracle
