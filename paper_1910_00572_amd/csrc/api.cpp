@@ -186,9 +186,11 @@ bool stream_plane_ok(int W, int H, size_t eb) {
 }
 
 // Launch shape of the step kernel, from measurements on MI355X.  Maps of
-// fewer than 512 64 x 16 tiles: streaming kernel, 8-row strips, 4 waves,
-// two slice buffers (512^2 x 72 FP32: 57.7 us; 16-row strips 68.5 us, two
-// theta chunks 61.9 us, the tiled kernel 78.7 us).  Larger maps: streaming
+// fewer than 512 64 x 16 tiles: streaming kernel, 4-row strips, 4 waves,
+// two slice buffers (512^2 x 72 FP32, one process: 52.8 us against 54.4 us
+// with 8-row strips, 61.0 us with 12-row strips, 56.9 us with 8-row strips
+// in two theta chunks and 62.3 us with 4-row strips in two; earlier, the tiled
+// kernel took 78.7 us).  Larger maps: streaming
 // kernel with 16-row strips, 8 waves and one slice buffer (1024^2 x 128:
 // FP32 332 us against 362 us tiled; BF16 278 us against 306-384 us for the
 // other streaming shapes).  The tiled kernel remains for planes of 1 GiB or
@@ -201,8 +203,10 @@ StepShape choose_shape(int W, int H, int T, int R, size_t eb) {
   int sh[5] = {64, 16, 256, 0, 2};
   if (stream_plane_ok(W, H, eb)) {
     if (tiled_tiles < 512) {
+      // four-row strips: twice the workgroups of eight-row strips (more waves
+      // per SIMD on small maps) at the cost of more halo rows per output
       sh[0] = 0;
-      sh[1] = 8;
+      sh[1] = 4;
       sh[2] = 256;
       sh[3] = 1;
     } else {

@@ -897,7 +897,7 @@ hipError_t launch_stream(const StepArgs* single, const StepArgs* jobs, const int
 // Instantiated launch shapes.  Tiled kernel: (TX, TY, NT).  Streaming
 // kernel: (TY rows per strip, waves, source-slice buffers).
 #define MCL_SHAPES(X) X(64, 16, 256) X(32, 16, 128)
-#define MCL_STREAM_SHAPES(X) X(8, 4, 2) X(12, 4, 2) X(16, 4, 2) X(8, 8, 1) X(16, 8, 1)
+#define MCL_STREAM_SHAPES(X) X(4, 4, 2) X(8, 4, 2) X(12, 4, 2) X(16, 4, 2) X(4, 8, 1) X(8, 8, 1) X(16, 8, 1)
 
 template <typename T, int R>
 hipError_t dispatch_shape(const KernelShape& k, const StepArgs* single, const StepArgs* jobs, const int32_t* bj,

@@ -67,8 +67,8 @@ def test_multi_tile_map_with_theta_chunks():
     _run_pair(occ, 0.1, 40, 1.0, 1.0, odo, check_every=5, tag="multitile")
 
 
-@pytest.mark.parametrize("shape", ["64,16,256,0", "32,16,128,0", "0,8,256,1,2", "0,12,256,2,2", "0,16,256,1,2",
-                                   "0,8,512,1,1", "0,16,512,1,1"])
+@pytest.mark.parametrize("shape", ["64,16,256,0", "32,16,128,0", "0,4,256,1,2", "0,8,256,1,2", "0,12,256,2,2",
+                                   "0,16,256,1,2", "0,4,512,2,1", "0,8,512,1,1", "0,16,512,1,1"])
 def test_every_kernel_shape(shape, monkeypatch):
     # the launch shape is chosen when the filter is created; each one must match the oracle
     monkeypatch.setenv("MCL_STEP_SHAPE", shape)
