@@ -250,7 +250,9 @@ size_t mcl_match_workspace_bytes(mcl_map map, int32_t n_theta, int32_t batch);
  * the scan update does).  out_cell: host int32 per query, j * W + i;
  * out_heading, out_dist: host int32 per query (nullable).  Runs in batches of
  * `batch` queries on the map's range table with dev_ws (caller-owned device
- * memory of at least mcl_match_workspace_bytes(map, n_theta, batch) bytes).
+ * memory of at least mcl_match_workspace_bytes(map, n_theta, batch) bytes);
+ * the next batch is quantised on the host while one runs, through two pinned
+ * host staging buffers that the call allocates and frees itself.
  * ESTATE without a range table; EINVAL for n_theta outside [1, 360], a table
  * deeper than 384 directions, W * H >= 2^30, batch * n_theta columns of 2 GiB
  * or more (batch * n_theta * 384 * 2 bytes for BF16 operands, * 4 for FP32),

@@ -842,11 +842,40 @@ mcl_status mcl_best_match(mcl_map map, int32_t n_theta, const float* ranges_m, i
   for (int64_t e = 0; e < static_cast<int64_t>(n_queries) * N; ++e)
     if (!isfinite(ranges_m[e])) return fail(MCL_EINVAL, "range %lld is not finite", static_cast<long long>(e));
   const double h = t.max_range / 256.0;
-  std::vector<int16_t> zq(static_cast<size_t>(batch) * N);
-  std::vector<int32_t> sz(batch);
-  std::vector<uint64_t> best(batch);
-  for (int q0 = 0; q0 < n_queries; q0 += batch) {
-    const int nq = std::min(batch, n_queries - q0);
+  if (n_queries == 0) return MCL_OK;
+  // Two pinned host staging sets: batch b + 1 is quantised on the host while
+  // batch b runs on the device (the device buffers are reused in stream order).
+  struct Staging {
+    int16_t* zq[2] = {nullptr, nullptr};
+    int32_t* sz[2] = {nullptr, nullptr};
+    uint64_t* best[2] = {nullptr, nullptr};
+    hipEvent_t done[2] = {nullptr, nullptr};
+    hipStream_t s = nullptr;
+    ~Staging() {
+      if (s) (void)hipStreamSynchronize(s);  // no copy may still target the staging on an early return
+      for (int i = 0; i < 2; ++i) {
+        if (done[i]) (void)hipEventDestroy(done[i]);
+        if (zq[i]) (void)hipHostFree(zq[i]);
+        if (sz[i]) (void)hipHostFree(sz[i]);
+        if (best[i]) (void)hipHostFree(best[i]);
+      }
+    }
+  } st;
+  for (int i = 0; i < 2; ++i) {
+    HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&st.zq[i]), static_cast<size_t>(batch) * N * sizeof(int16_t)),
+            "pinned staging");
+    HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&st.sz[i]), static_cast<size_t>(batch) * sizeof(int32_t)),
+            "pinned staging");
+    HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&st.best[i]), static_cast<size_t>(batch) * sizeof(uint64_t)),
+            "pinned staging");
+    HIP_TRY(hipEventCreateWithFlags(&st.done[i], hipEventDisableTiming), "event");
+  }
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+  st.s = s;
+  const int nbatch = (n_queries + batch - 1) / batch;
+  auto quantise = [&](int bi) {
+    const int q0 = bi * batch, nq = std::min(batch, n_queries - q0);
+    int16_t* zq = st.zq[bi & 1];
     for (int p = 0; p < nq; ++p) {
       int32_t ss = 0;
       for (int b = 0; b < N; ++b) {
@@ -856,19 +885,33 @@ mcl_status mcl_best_match(mcl_map map, int32_t n_theta, const float* ranges_m, i
         zq[static_cast<size_t>(p) * N + b] = static_cast<int16_t>(q);
         ss += q * q;
       }
-      sz[p] = ss;
+      st.sz[bi & 1][p] = ss;
     }
-    HIP_TRY(match_launch(t, map->free8, map->W, map->H, map->pitch, n_theta, zq.data(), sz.data(), nq, dev_ws,
-                         best.data(), static_cast<hipStream_t>(stream)),
-            "best match");
+  };
+  auto decode = [&](int bi) {
+    const int q0 = bi * batch, nq = std::min(batch, n_queries - q0);
     for (int p = 0; p < nq; ++p) {
-      const uint64_t key = best[p];
+      const uint64_t key = st.best[bi & 1][p];
       const bool none = key == ~0ull;  // no free cell at all
       out_cell[q0 + p] = none ? -1 : static_cast<int32_t>(key & ((1ull << 30) - 1));
       if (out_heading) out_heading[q0 + p] = none ? -1 : static_cast<int32_t>((key >> 30) & 511u);
       if (out_dist) out_dist[q0 + p] = none ? -1 : static_cast<int32_t>(key >> 39);
     }
+  };
+  for (int bi = 0; bi < nbatch; ++bi) {
+    quantise(bi);
+    const int nq = std::min(batch, n_queries - bi * batch);
+    HIP_TRY(match_launch(t, map->free8, map->W, map->H, map->pitch, n_theta, st.zq[bi & 1], st.sz[bi & 1], nq,
+                         dev_ws, st.best[bi & 1], s),
+            "best match");
+    HIP_TRY(hipEventRecord(st.done[bi & 1], s), "event");
+    if (bi > 0) {
+      HIP_TRY(hipEventSynchronize(st.done[(bi - 1) & 1]), "best match");
+      decode(bi - 1);
+    }
   }
+  HIP_TRY(hipEventSynchronize(st.done[(nbatch - 1) & 1]), "best match");
+  decode(nbatch - 1);
   return MCL_OK;
 }
 

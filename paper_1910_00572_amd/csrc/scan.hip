@@ -1363,10 +1363,7 @@ hipError_t match_launch(const ScanTable& t, const uint8_t* free8, int W, int H, 
   }
 #undef MCL_MATCH
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  if ((e = hipMemcpyAsync(best_host, best, static_cast<size_t>(nq) * sizeof(uint64_t), hipMemcpyDeviceToHost, s)) !=
-      hipSuccess)
-    return e;
-  return hipStreamSynchronize(s);
+  return hipMemcpyAsync(best_host, best, static_cast<size_t>(nq) * sizeof(uint64_t), hipMemcpyDeviceToHost, s);
 }
 
 int scan_tiles(int cells) { return (cells + kTileCells - 1) / kTileCells; }

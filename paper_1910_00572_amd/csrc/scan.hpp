@@ -54,7 +54,10 @@ hipError_t scan_launch(const ScanLaunch& L, const float* ranges_m, double sigma_
 hipError_t scan_sampled_launch(const ScanLaunch& L, const float* ranges_m, double sigma_m, const uint8_t* mask,
                                int32_t* list, int32_t* pos);
 // Best match of nq quantised query scans over every free state (map
-// difficulty): synchronous; best_host[p] = (D << 39) | (k << 30) | dense cell.
+// difficulty), enqueued on s: copies the queries in, runs the product and
+// copies best_host[p] = (D << 39) | (k << 30) | dense cell out.  The host
+// buffers must stay valid (and be pinned for the copies to be asynchronous)
+// until the stream has reached that point.
 size_t match_workspace_bytes(const ScanTable& t, int cells, int n_theta, int batch);
 hipError_t match_launch(const ScanTable& t, const uint8_t* free8, int W, int H, int pitch, int n_theta,
                         const int16_t* zq_host, const int32_t* sz_host, int nq, void* ws, uint64_t* best_host,
