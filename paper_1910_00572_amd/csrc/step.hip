@@ -557,7 +557,9 @@ __device__ __forceinline__ void stream_body(const StepArgs& a, const int blk, co
   constexpr bool ONE_BARRIER = WAVES <= 4;
   constexpr int RS = 2 * R + (ONE_BARRIER ? 2 : 1) * GW;
   constexpr int TAPS = 2 * R + 1;
-  constexpr int LP = TY + 4;       // ring lane pitch (floats): conflict-free 16-byte accesses
+  // ring lane pitch (floats): an odd number of 16-byte units, so the 64
+  // lanes' 16-byte accesses fall on distinct banks in every pass
+  constexpr int LP = (TY / 4) % 2 == 1 ? TY : TY + 4;
   constexpr int EB = Elt<T>::BYTES;
   static_assert(TY % 4 == 0, "rows per strip must be a multiple of 4");
   static_assert(NBUF == 1 || NBUF == 2, "one or two source-slice buffers");
