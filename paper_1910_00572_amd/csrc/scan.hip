@@ -173,9 +173,15 @@ __host__ __device__ inline int64_t tiled_offset(int64_t cell, int beta, int64_t 
 // kNChunk*32 channels the accumulators and ln B stay in registers between
 // the search for the tile's reference state and the write of L - L_ref; more
 // channels recompute the product once.
-template <typename OP, typename T, int MODE, int NCH, int KPAD>
+//
+// BL: the whole circulant operand (every channel block, depth KPAD) is staged
+// once per workgroup in LDS, in the order the MFMA reads it ([block][depth
+// step][lane]), so the four waves share it instead of each streaming it from
+// L2; only when all blocks fit one pass (nblocks == NCH) and KPAD > 0.
+template <typename OP, typename T, int MODE, int NCH, int KPAD, bool BL = false>
 __global__ __launch_bounds__(kScanThreads) void scan_gemm_kernel(ScanArgs a) {
   constexpr int kNChunk = NCH;  // 32-wide channel blocks held in accumulators at once
+  static_assert(!BL || KPAD > 0, "the staged operand needs a compile-time depth");
   __shared__ float red_v[kScanThreads];
   __shared__ int red_i[kScanThreads];
   __shared__ int red_d[kScanThreads];
@@ -197,6 +203,24 @@ __global__ __launch_bounds__(kScanThreads) void scan_gemm_kernel(ScanArgs a) {
   const int nblocks = a.npad / 32;
   const int nchunks = (nblocks + kNChunk - 1) / kNChunk;
 
+  using Vec = typename Mfma<OP>::Vec;
+  constexpr int KSB = KPAD > 0 ? KPAD / KSTEP : 1;  // depth steps of the staged operand
+  __shared__ Vec bsh[BL ? NCH * KSB * 64 : 1];
+  if constexpr (BL) {
+    // 16-byte pieces of the [npad][kpad] operand, column by column (the
+    // global reads are contiguous), written to their MFMA-order slots
+    constexpr int PPC = KPAD / HALF;  // pieces per column
+    const __amdgpu_buffer_rsrc_t rsb = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<OP*>(ct), static_cast<short>(0), static_cast<int>(a.npad * a.kpad * sizeof(OP)), 0x00020000);
+    for (int e = t; e < NCH * 32 * PPC; e += kScanThreads) {
+      const int c = e / PPC, pc = e - c * PPC;
+      const int st = (pc * HALF) / KSTEP, hf = ((pc * HALF) % KSTEP) / HALF;
+      bsh[((c >> 5) * KSB + st) * 64 + hf * 32 + (c & 31)] = __builtin_bit_cast(
+          Vec, __builtin_amdgcn_raw_buffer_load_b128(rsb, static_cast<uint32_t>(e * 16), 0, 0));
+    }
+    __syncthreads();
+  }
+
   f32x16 acc[kNChunk];
   // Depth loop.  The operands of a step are loaded four steps ahead (a ring
   // of four register sets): the A pieces stream from HBM, the B pieces (the
@@ -207,7 +231,6 @@ __global__ __launch_bounds__(kScanThreads) void scan_gemm_kernel(ScanArgs a) {
   // repeat the last step's address and are never used.  Channel blocks past
   // the last one (a final partial chunk) repeat the last block's operand; the
   // epilogue ignores them.
-  using Vec = typename Mfma<OP>::Vec;
   constexpr int PA = 4;               // prefetch depth (steps)
   constexpr int EB = sizeof(OP);
   const int nsteps = a.kpad / KSTEP;  // a multiple of PA: kpad is a multiple of 64
@@ -226,6 +249,12 @@ __global__ __launch_bounds__(kScanThreads) void scan_gemm_kernel(ScanArgs a) {
     v = __builtin_bit_cast(Vec, __builtin_amdgcn_raw_buffer_load_b128(ra, va, so, 0));
   };
   auto load_b = [&](int nc, int step, Vec (&v)[kNChunk]) {
+    if constexpr (BL) {
+      const int st = min(step, KSB - 1);
+#pragma unroll
+      for (int b = 0; b < kNChunk; ++b) v[b] = bsh[(b * KSB + st) * 64 + lane];
+      return;
+    }
     const uint32_t so = static_cast<uint32_t>(min(step, nsteps - 1) * KSTEP * EB);
 #pragma unroll
     for (int b = 0; b < kNChunk; ++b) {
@@ -1165,6 +1194,23 @@ hipError_t scan_launch(const ScanLaunch& L, const float* ranges_m, double sigma_
   const dim3 g1(a.tiles), b1(kScanThreads);
   // channel blocks per pass: all of them when they fit (no recomputation)
   const int nch = std::min(kMaxNChunk, ca.npad / 32);
+  // BF16 operands, depth 384, at most three blocks in one pass: the operand
+  // (at most 72 KB) is staged in LDS, two workgroups per compute unit
+  const bool stage_b = !dout && !t.f32 && t.kpad == 384 && ca.npad / 32 <= 3;
+  if (stage_b) {
+    switch (L.dtype * 8 + nch) {
+#define MCL_GEMM_BL(DT, T_)                                                                                   \
+  case DT * 8 + 1: hipLaunchKernelGGL((scan_gemm_kernel<__bf16, T_, 0, 1, 384, true>), g1, b1, 0, L.stream, a); break; \
+  case DT * 8 + 2: hipLaunchKernelGGL((scan_gemm_kernel<__bf16, T_, 0, 2, 384, true>), g1, b1, 0, L.stream, a); break; \
+  case DT * 8 + 3: hipLaunchKernelGGL((scan_gemm_kernel<__bf16, T_, 0, 3, 384, true>), g1, b1, 0, L.stream, a); break;
+      MCL_GEMM_BL(0, float)
+      MCL_GEMM_BL(1, __bf16)
+      MCL_GEMM_BL(2, _Float16)
+#undef MCL_GEMM_BL
+      default: return hipErrorInvalidValue;
+    }
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
   // depth 384 (321..384 directions, e.g. 360) has a fully unrolled depth loop
 #define MCL_GEMM_K(OP, T, MODE, KP)                                                                    \
   switch (nch) {                                                                                       \
@@ -1186,7 +1232,7 @@ hipError_t scan_launch(const ScanLaunch& L, const float* ranges_m, double sigma_
     else MCL_GEMM(__bf16, float, 1);
     return hipGetLastError();
   }
-  switch (L.dtype * 2 + (t.f32 ? 1 : 0)) {
+  if (!stage_b) switch (L.dtype * 2 + (t.f32 ? 1 : 0)) {
     case 0: MCL_GEMM(__bf16, float, 0); break;
     case 1: MCL_GEMM(float, float, 0); break;
     case 2: MCL_GEMM(__bf16, __bf16, 0); break;
