@@ -238,7 +238,9 @@ mcl_status mcl_dither(const float* dev_intensity, int32_t width, int32_t height,
                       void* stream);
 
 /* Device bytes mcl_best_match needs for batches of up to `batch` queries
- * (0 if the map has no range table or the arguments are out of range). */
+ * (0 if the map has no range table or the arguments are out of range): the
+ * batch's circulant columns plus one 4-byte key per 128 cells and column,
+ * about 4 * (H * pitch / 128) * batch * n_theta bytes. */
 size_t mcl_match_workspace_bytes(mcl_map map, int32_t n_theta, int32_t batch);
 
 /* best_match (sync): for each query scan, the state that matches it best
@@ -254,7 +256,8 @@ size_t mcl_match_workspace_bytes(mcl_map map, int32_t n_theta, int32_t batch);
  * the next batch is quantised on the host while one runs, through two pinned
  * host staging buffers that the call allocates and frees itself.
  * ESTATE without a range table; EINVAL for n_theta outside [1, 360], a table
- * deeper than 384 directions, W * H >= 2^30, batch * n_theta columns of 2 GiB
+ * deeper than 384 directions, H * pitch >= 2^30 (pitch = W rounded up to a
+ * multiple of 8), batch * n_theta columns of 2 GiB
  * or more (batch * n_theta * 384 * 2 bytes for BF16 operands, * 4 for FP32),
  * non-finite ranges or NULL pointers; ENOMEM for a small workspace. */
 mcl_status mcl_best_match(mcl_map map, int32_t n_theta, const float* ranges_m, int32_t n_queries,

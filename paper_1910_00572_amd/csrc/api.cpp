@@ -831,8 +831,8 @@ mcl_status mcl_best_match(mcl_map map, int32_t n_theta, const float* ranges_m, i
   if (t.n_dirs == 0) return fail(MCL_ESTATE, "the map has no range table");
   if (n_theta < 1 || n_theta > kMaxTheta) return fail(MCL_EINVAL, "n_theta must be in [1, %d]", kMaxTheta);
   if (t.kpad > 384) return fail(MCL_EINVAL, "best_match supports tables of at most 384 directions");
-  if (static_cast<int64_t>(map->W) * map->H >= (static_cast<int64_t>(1) << 30))
-    return fail(MCL_EINVAL, "best_match supports maps of fewer than 2^30 cells");
+  if (static_cast<int64_t>(map->pitch) * map->H >= (static_cast<int64_t>(1) << 30))
+    return fail(MCL_EINVAL, "best_match supports maps of fewer than 2^30 padded cells");
   if (n_queries < 0 || batch < 1) return fail(MCL_EINVAL, "n_queries must be >= 0 and batch >= 1");
   if (n_queries > 0 && (!ranges_m || !out_cell)) return fail(MCL_EINVAL, "NULL ranges or output");
   const size_t need = mcl_match_workspace_bytes(map, n_theta, batch);
@@ -893,7 +893,8 @@ mcl_status mcl_best_match(mcl_map map, int32_t n_theta, const float* ranges_m, i
     for (int p = 0; p < nq; ++p) {
       const uint64_t key = st.best[bi & 1][p];
       const bool none = key == ~0ull;  // no free cell at all
-      out_cell[q0 + p] = none ? -1 : static_cast<int32_t>(key & ((1ull << 30) - 1));
+      const int64_t cell = static_cast<int64_t>(key & ((1ull << 30) - 1));  // j * pitch + i
+      out_cell[q0 + p] = none ? -1 : static_cast<int32_t>(cell / map->pitch * map->W + cell % map->pitch);
       if (out_heading) out_heading[q0 + p] = none ? -1 : static_cast<int32_t>((key >> 30) & 511u);
       if (out_dist) out_dist[q0 + p] = none ? -1 : static_cast<int32_t>(key >> 39);
     }

@@ -856,23 +856,34 @@ __global__ __launch_bounds__(kScanThreads) void sampled_apply_kernel(SampledArgs
 // For a batch of query scans, the free cell q and heading k whose expected scan
 // is closest (smallest exact D, heading offset 0): the dense product of the
 // range table with the circulant columns of every (query, heading), reduced by
-// min instead of exponentiated.  A 64-bit key (D, k, dense q) orders the
-// candidates as the stated tie rule does (lowest k * H * W + q), so one min
-// suffices: each workgroup takes the minimum over its cells per column, then
-// over the columns of one query, and folds it into best[query] with a 64-bit
-// atomic min (order-free, so the result does not depend on scheduling).
+// min instead of exponentiated.  A 64-bit key (D, k, cell) orders the
+// candidates as the stated tie rule does (lowest k * H * W + q: the padded
+// cell index j * pitch + i has the dense order on candidate cells), so one
+// min suffices.  The product kernel stores each workgroup's minimum per
+// column; a second pass takes the minimum per query (no atomics, so the result
+// does not depend on scheduling).
 struct MatchArgs {
   const void* rq;          // MFMA-tiled range table
   const int32_t* sr;       // [cells] sum of squares
   const uint8_t* free8;    // [cells] free cells (pitch layout; 0 outside the grid)
   const void* ct;          // circulant columns (column = query * n_theta + k), MFMA-tiled per 32 columns
   const int32_t* sz;       // [batch] sum of squared counts of each query
-  uint64_t* best;          // [batch], all ones before the launch
-  int32_t cells, pitch, W, n_theta, ncols, ncols_pad, kpad;
+  uint32_t* keys;          // [tiles][ncols_pad]: per workgroup and column, min of (D << 7 | local cell)
+  uint64_t* best;          // [batch]
+  int32_t cells, pitch, W, n_theta, ncols, ncols_pad, kpad, tiles;
   uint32_t rq_bytes;
+  uint64_t inv_theta;      // ceil(2^40 / n_theta): column / n_theta = (column * inv_theta) >> 40
 };
 
 constexpr uint64_t kNoKey = ~0ull;
+
+// column / n_theta without a division: exact for columns below 2^24 (the
+// column operand's 2 GiB limit keeps them there) and n_theta <= 360: the
+// product stays below 2^64 and the reciprocal's rounding error below 2^-16 <
+// 1 / n_theta
+__device__ inline int col_query(int c, uint64_t inv_theta) {
+  return static_cast<int>((static_cast<uint64_t>(c) * inv_theta) >> 40);
+}
 
 // One workgroup: 128 cells (32 per wave, A operand in registers for the whole
 // depth) against every column block of the batch.  A block of 32 columns is
@@ -880,8 +891,7 @@ constexpr uint64_t kNoKey = ~0ull;
 // reads it ([depth step][lane]), so all four waves share it.  Within the
 // workgroup a candidate is a 32-bit key (D << 7 | local cell); D < 2^25 for
 // any table of at most 384 directions, so the key is exact.  Per block, one
-// wave in turn widens the per-column minima to (D, k, dense cell) keys and
-// folds them per query into best[] with a 64-bit atomic min.
+// wave in turn takes the minimum over the four waves and stores it.
 template <typename OP, int KPAD>
 __global__ __launch_bounds__(kScanThreads) void match_gemm_kernel(MatchArgs a) {
   constexpr int KSTEP = Mfma<OP>::KSTEP, HALF = Mfma<OP>::HALF, EB = sizeof(OP);
@@ -934,13 +944,16 @@ __global__ __launch_bounds__(kScanThreads) void match_gemm_kernel(MatchArgs a) {
     }
   }
   __syncthreads();
-  for (int cb = 0; cb < ncb; ++cb) {
-    // prefetch the next block into registers (past the end the loads return zeros)
-    Vec nx[PER];
+  // One column block per call.  The loads of block cb + 2 are issued here and
+  // stored to LDS one call later, so each has a whole block's work to arrive;
+  // block cb + 1 (loaded one call ago) is stored to the other LDS buffer.
+  // ncb is even (the host pads the columns to 64), so the loop below runs
+  // the calls in pairs with compile-time register sets.
+  auto block = [&](int cb, Vec (&ld)[PER], Vec (&stv)[PER]) {
 #pragma unroll
     for (int u = 0; u < PER; ++u)
-      nx[u] = __builtin_bit_cast(Vec, __builtin_amdgcn_raw_buffer_load_b128(
-                  rb, static_cast<uint32_t>(((cb + 1) * BLK + t + u * kScanThreads) * 16), 0, 0));
+      ld[u] = __builtin_bit_cast(Vec, __builtin_amdgcn_raw_buffer_load_b128(
+                  rb, static_cast<uint32_t>(((cb + 2) * BLK + t + u * kScanThreads) * 16), 0, 0));
     const Vec* B = bs[cb & 1];
     Vec bf[PB];
 #pragma unroll
@@ -955,7 +968,7 @@ __global__ __launch_bounds__(kScanThreads) void match_gemm_kernel(MatchArgs a) {
     }
     // column of this lane; key = (Sz + Sr - 2X) << 7 | local cell, exact in 32 bits
     const int c = cb * 32 + col;
-    const int p = c < a.ncols ? c / a.n_theta : 0;
+    const int p = c < a.ncols ? col_query(c, a.inv_theta) : 0;
     const uint32_t sz7 = static_cast<uint32_t>(a.sz[p]) << 7;
     uint32_t m = ~0u;
 #pragma unroll
@@ -967,37 +980,52 @@ __global__ __launch_bounds__(kScanThreads) void match_gemm_kernel(MatchArgs a) {
     m = o < m ? o : m;
     if (half == 0) wmin[cb & 1][wv][col] = m;
 #pragma unroll
-    for (int u = 0; u < PER; ++u) bs[(cb + 1) & 1][t + u * kScanThreads] = nx[u];
+    for (int u = 0; u < PER; ++u) bs[(cb + 1) & 1][t + u * kScanThreads] = stv[u];
     __syncthreads();
-    if (wv == (cb & 3)) {
-      // lanes 0..31: one column each; the columns of one query are contiguous
-      const int cc = cb * 32 + lane;
-      uint64_t b = kNoKey;
-      int q = -1;
-      if (lane < 32 && cc < a.ncols) {
-        uint32_t w = wmin[cb & 1][0][lane];
+    if (wv == (cb & 3) && lane < 32) {
+      // the workgroup's minimum per column, stored for the per-query pass
+      uint32_t w = wmin[cb & 1][0][lane];
 #pragma unroll
-        for (int v = 1; v < kScanThreads / 64; ++v) w = wmin[cb & 1][v][lane] < w ? wmin[cb & 1][v][lane] : w;
-        q = cc / a.n_theta;
-        if (w != ~0u) {
-          const int cell = blockIdx.x * kTileCells + static_cast<int>(w & 127u);
-          const int j = cell / a.pitch, x = cell - j * a.pitch;
-          const uint64_t k = static_cast<uint64_t>(cc - q * a.n_theta);
-          b = (static_cast<uint64_t>(w >> 7) << 39) | (k << 30) | (static_cast<uint64_t>(j) * a.W + x);
-        }
-      }
-      // segmented suffix minimum: lane t ends with the minimum of its query's lanes from t on
-#pragma unroll
-      for (int off = 1; off < 32; off <<= 1) {
-        const uint64_t ob = __shfl_down(b, off);
-        const int oq = __shfl_down(q, off);
-        if (lane + off < 64 && oq == q) b = ob < b ? ob : b;
-      }
-      const int pq = __shfl_up(q, 1);
-      if (q >= 0 && (lane == 0 || pq != q) && b != kNoKey)
-        __hip_atomic_fetch_min(a.best + q, b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      for (int v = 1; v < kScanThreads / 64; ++v) w = wmin[cb & 1][v][lane] < w ? wmin[cb & 1][v][lane] : w;
+      a.keys[static_cast<int64_t>(blockIdx.x) * a.ncols_pad + cb * 32 + lane] = w;
     }
+  };
+  Vec nxA[PER], nxB[PER];
+#pragma unroll
+  for (int u = 0; u < PER; ++u)
+    nxA[u] = __builtin_bit_cast(Vec, __builtin_amdgcn_raw_buffer_load_b128(
+                 rb, static_cast<uint32_t>((BLK + t + u * kScanThreads) * 16), 0, 0));
+  for (int cb = 0; cb < ncb; cb += 2) {
+    block(cb, nxB, nxA);
+    block(cb + 1, nxA, nxB);
   }
+}
+
+// Per query: the minimum over workgroups and headings of the 64-bit key
+// (D << 39) | (k << 30) | cell, cell in the padded layout (its order is the
+// dense order on candidate cells).  One workgroup per query, no atomics.
+__global__ __launch_bounds__(kScanThreads) void match_reduce_kernel(MatchArgs a) {
+  __shared__ uint64_t red[kScanThreads];
+  const int t = threadIdx.x, p = blockIdx.x;
+  uint64_t m = kNoKey;
+  const int64_t n = static_cast<int64_t>(a.tiles) * a.n_theta;
+  const bool recip = n < (int64_t{1} << 24);  // (tile, k) from e without a 64-bit division
+  for (int64_t e = t; e < n; e += kScanThreads) {
+    const int tile = recip ? col_query(static_cast<int>(e), a.inv_theta) : static_cast<int>(e / a.n_theta);
+    const int k = static_cast<int>(e - static_cast<int64_t>(tile) * a.n_theta);
+    const uint32_t w = a.keys[static_cast<int64_t>(tile) * a.ncols_pad + static_cast<int64_t>(p) * a.n_theta + k];
+    if (w == ~0u) continue;
+    const uint64_t key = (static_cast<uint64_t>(w >> 7) << 39) | (static_cast<uint64_t>(k) << 30) |
+                         static_cast<uint64_t>(tile * kTileCells + static_cast<int>(w & 127u));
+    m = key < m ? key : m;
+  }
+  red[t] = m;
+  __syncthreads();
+  for (int st = kScanThreads / 2; st > 0; st >>= 1) {
+    if (t < st && red[t + st] < red[t]) red[t] = red[t + st];
+    __syncthreads();
+  }
+  if (t == 0) a.best[p] = red[0];
 }
 
 // Circulant columns of a batch of queries: C[p * n_theta + k][beta] = zq_p[(beta - s_k) mod N],
@@ -1328,8 +1356,8 @@ hipError_t scan_sampled_launch(const ScanLaunch& L, const float* ranges_m, doubl
 
 size_t match_workspace_bytes(const ScanTable& t, int cells, int n_theta, int batch) {
   if (t.n_dirs == 0 || batch < 1) return 0;
-  (void)cells;
-  const int64_t ncols_pad = round_up_i(batch * n_theta, 32);
+  const int64_t tiles = (static_cast<int64_t>(cells) + kTileCells - 1) / kTileCells;
+  const int64_t ncols_pad = round_up_i(batch * n_theta, 64);  // an even number of 32-column blocks
   const int64_t ct_bytes = ncols_pad * t.kpad * (t.f32 ? 4 : 2);
   if (ct_bytes >= (int64_t{1} << 31)) return 0;  // the column operand is addressed with 31-bit offsets
   Carver c(nullptr);
@@ -1337,6 +1365,7 @@ size_t match_workspace_bytes(const ScanTable& t, int cells, int n_theta, int bat
   c.take(static_cast<size_t>(batch) * t.n_dirs * sizeof(int16_t));
   c.take(static_cast<size_t>(batch) * sizeof(int32_t));
   c.take(static_cast<size_t>(batch) * sizeof(uint64_t));
+  c.take(static_cast<size_t>(tiles * ncols_pad) * sizeof(uint32_t));
   return c.off;
 }
 
@@ -1344,13 +1373,14 @@ hipError_t match_launch(const ScanTable& t, const uint8_t* free8, int W, int H, 
                         const int16_t* zq_host, const int32_t* sz_host, int nq, void* ws, uint64_t* best_host,
                         hipStream_t s) {
   const int cells = H * pitch;
-  const int ncols = nq * n_theta, ncols_pad = round_up_i(ncols, 32);
+  const int ncols = nq * n_theta, ncols_pad = round_up_i(ncols, 64);
   const int tiles = (cells + kTileCells - 1) / kTileCells;
   Carver c(ws);
   void* ct = c.take(static_cast<size_t>(ncols_pad) * t.kpad * (t.f32 ? 4 : 2));
   int16_t* zq = static_cast<int16_t*>(c.take(static_cast<size_t>(nq) * t.n_dirs * sizeof(int16_t)));
   int32_t* sz = static_cast<int32_t*>(c.take(static_cast<size_t>(nq) * sizeof(int32_t)));
   uint64_t* best = static_cast<uint64_t*>(c.take(static_cast<size_t>(nq) * sizeof(uint64_t)));
+  uint32_t* keys = static_cast<uint32_t*>(c.take(static_cast<size_t>(tiles) * ncols_pad * sizeof(uint32_t)));
   hipError_t e = hipMemcpyAsync(zq, zq_host, static_cast<size_t>(nq) * t.n_dirs * sizeof(int16_t),
                                 hipMemcpyHostToDevice, s);
   if (e != hipSuccess) return e;
@@ -1383,7 +1413,9 @@ hipError_t match_launch(const ScanTable& t, const uint8_t* free8, int W, int H, 
   a.free8 = free8;
   a.ct = ct;
   a.sz = sz;
+  a.keys = keys;
   a.best = best;
+  a.tiles = tiles;
   a.cells = cells;
   a.pitch = pitch;
   a.W = W;
@@ -1392,6 +1424,7 @@ hipError_t match_launch(const ScanTable& t, const uint8_t* free8, int W, int H, 
   a.ncols_pad = ncols_pad;
   a.kpad = t.kpad;
   a.rq_bytes = static_cast<uint32_t>(t.rq_bytes);
+  a.inv_theta = ((uint64_t{1} << 40) + static_cast<uint64_t>(n_theta) - 1) / static_cast<uint64_t>(n_theta);
   // the A operand is held in registers for the whole table depth (at most 384)
 #define MCL_MATCH(KP)                                                                                   \
   case KP:                                                                                              \
@@ -1408,6 +1441,8 @@ hipError_t match_launch(const ScanTable& t, const uint8_t* free8, int W, int H, 
     default: return hipErrorInvalidValue;
   }
 #undef MCL_MATCH
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(match_reduce_kernel, dim3(nq), dim3(kScanThreads), 0, s, a);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   return hipMemcpyAsync(best_host, best, static_cast<size_t>(nq) * sizeof(uint64_t), hipMemcpyDeviceToHost, s);
 }

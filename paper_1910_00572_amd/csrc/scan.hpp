@@ -55,7 +55,7 @@ hipError_t scan_sampled_launch(const ScanLaunch& L, const float* ranges_m, doubl
                                int32_t* list, int32_t* pos);
 // Best match of nq quantised query scans over every free state (map
 // difficulty), enqueued on s: copies the queries in, runs the product and
-// copies best_host[p] = (D << 39) | (k << 30) | dense cell out.  The host
+// copies best_host[p] = (D << 39) | (k << 30) | cell out (cell = j * pitch + i).  The host
 // buffers must stay valid (and be pinned for the copies to be asynchronous)
 // until the stream has reached that point.
 size_t match_workspace_bytes(const ScanTable& t, int cells, int n_theta, int batch);
