@@ -860,8 +860,8 @@ __global__ __launch_bounds__(kScanThreads) void sampled_apply_kernel(SampledArgs
 // candidates as the stated tie rule does (lowest k * H * W + q: the padded
 // cell index j * pitch + i has the dense order on candidate cells), so one
 // min suffices.  The product kernel stores each workgroup's minimum per
-// column; a second pass takes the minimum per query (no atomics, so the result
-// does not depend on scheduling).
+// column; a second pass takes the minimum per query (a min is order-free, so
+// the result does not depend on scheduling).
 struct MatchArgs {
   const void* rq;          // MFMA-tiled range table
   const int32_t* sr;       // [cells] sum of squares
@@ -1003,14 +1003,18 @@ __global__ __launch_bounds__(kScanThreads) void match_gemm_kernel(MatchArgs a) {
 
 // Per query: the minimum over workgroups and headings of the 64-bit key
 // (D << 39) | (k << 30) | cell, cell in the padded layout (its order is the
-// dense order on candidate cells).  One workgroup per query, no atomics.
+// dense order on candidate cells).  Grid (queries, kReduceChunks): each
+// workgroup takes one share of the product's workgroups and folds its
+// minimum into best[query] with a 64-bit atomic min (order-free).
+constexpr int kReduceChunks = 16;
 __global__ __launch_bounds__(kScanThreads) void match_reduce_kernel(MatchArgs a) {
   __shared__ uint64_t red[kScanThreads];
   const int t = threadIdx.x, p = blockIdx.x;
   uint64_t m = kNoKey;
   const int64_t n = static_cast<int64_t>(a.tiles) * a.n_theta;
+  const int64_t e0 = n * blockIdx.y / gridDim.y, e1 = n * (blockIdx.y + 1) / gridDim.y;
   const bool recip = n < (int64_t{1} << 24);  // (tile, k) from e without a 64-bit division
-  for (int64_t e = t; e < n; e += kScanThreads) {
+  for (int64_t e = e0 + t; e < e1; e += kScanThreads) {
     const int tile = recip ? col_query(static_cast<int>(e), a.inv_theta) : static_cast<int>(e / a.n_theta);
     const int k = static_cast<int>(e - static_cast<int64_t>(tile) * a.n_theta);
     const uint32_t w = a.keys[static_cast<int64_t>(tile) * a.ncols_pad + static_cast<int64_t>(p) * a.n_theta + k];
@@ -1025,7 +1029,7 @@ __global__ __launch_bounds__(kScanThreads) void match_reduce_kernel(MatchArgs a)
     if (t < st && red[t + st] < red[t]) red[t] = red[t + st];
     __syncthreads();
   }
-  if (t == 0) a.best[p] = red[0];
+  if (t == 0 && red[0] != kNoKey) __hip_atomic_fetch_min(a.best + p, red[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Circulant columns of a batch of queries: C[p * n_theta + k][beta] = zq_p[(beta - s_k) mod N],
@@ -1038,28 +1042,44 @@ struct MatchCtArgs {
   int16_t s[kMaxTheta];
 };
 
+// One thread per 16-byte piece: HALF consecutive depths of one column, which
+// the MFMA-tiled order keeps together ([block][depth step][lane half][column][HALF]).
+template <typename OP>
+__device__ inline void match_ct_piece(const MatchCtArgs& a, int64_t piece) {
+  constexpr int KSTEP = Mfma<OP>::KSTEP, HALF = Mfma<OP>::HALF;
+  const int ppc = a.kpad / HALF;  // pieces per column
+  const int c = static_cast<int>(piece / ppc), beta0 = static_cast<int>(piece - static_cast<int64_t>(c) * ppc) * HALF;
+  const int st = beta0 / KSTEP, hf = (beta0 - st * KSTEP) / HALF;
+  const int64_t dst = (static_cast<int64_t>(c / 32) * (a.kpad / KSTEP) + st) * 64 + hf * 32 + (c & 31);
+  float v[HALF];
+  const bool live = c < a.ncols;
+  const int p = live ? c / a.n_theta : 0, k = live ? c - p * a.n_theta : 0;
+  int b = (beta0 - a.s[k]) % a.n_dirs;
+  if (b < 0) b += a.n_dirs;
+#pragma unroll
+  for (int h = 0; h < HALF; ++h) {
+    v[h] = live && beta0 + h < a.n_dirs ? static_cast<float>(a.zq[static_cast<int64_t>(p) * a.n_dirs + b]) : 0.f;
+    b = b + 1 == a.n_dirs ? 0 : b + 1;
+  }
+  typename Mfma<OP>::Vec out;
+  if constexpr (sizeof(OP) == 4) {
+    out = make_float4(v[0], v[1], v[2], v[3]);
+  } else {
+#pragma unroll
+    for (int h = 0; h < HALF; ++h) out[h] = static_cast<OP>(v[h]);
+  }
+  static_cast<typename Mfma<OP>::Vec*>(a.ct)[dst] = out;
+}
+
 __global__ void match_ct_kernel(MatchCtArgs a) {
   const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (idx < a.nq) a.best[idx] = kNoKey;
-  if (idx >= static_cast<int64_t>(a.ncols_pad) * a.kpad) return;
-  const int c = static_cast<int>(idx / a.kpad), beta = static_cast<int>(idx % a.kpad);
-  // MFMA-tiled: per 32-column block, [depth step][lane half][column][HALF]
-  const int kstep = a.f32 ? Mfma<float>::KSTEP : Mfma<__bf16>::KSTEP;
-  const int hf = a.f32 ? Mfma<float>::HALF : Mfma<__bf16>::HALF;
-  const int st = beta / kstep, within = beta - st * kstep;
-  const int64_t dst = ((static_cast<int64_t>(c / 32) * (a.kpad / kstep) + st) * 64 + (within / hf) * 32 + (c & 31)) * hf +
-                      within % hf;
-  float v = 0.f;
-  if (c < a.ncols && beta < a.n_dirs) {
-    const int p = c / a.n_theta, k = c - p * a.n_theta;
-    int b = (beta - a.s[k]) % a.n_dirs;
-    if (b < 0) b += a.n_dirs;
-    v = static_cast<float>(a.zq[static_cast<int64_t>(p) * a.n_dirs + b]);
-  }
+  const int64_t pieces = static_cast<int64_t>(a.ncols_pad) * a.kpad / (a.f32 ? Mfma<float>::HALF : Mfma<__bf16>::HALF);
+  if (idx >= pieces) return;
   if (a.f32)
-    static_cast<float*>(a.ct)[dst] = v;
+    match_ct_piece<float>(a, idx);
   else
-    static_cast<__bf16*>(a.ct)[dst] = static_cast<__bf16>(v);
+    match_ct_piece<__bf16>(a, idx);
 }
 
 // ---- map table: quantise ranges ---------------------------------------------------------
@@ -1404,7 +1424,8 @@ hipError_t match_launch(const ScanTable& t, const uint8_t* free8, int W, int H, 
     if (v < 0) v += t.n_dirs;
     ca.s[k] = static_cast<int16_t>(v);
   }
-  const int64_t nct = static_cast<int64_t>(ncols_pad) * t.kpad;
+  // one thread per 16-byte piece of the operand, and at least one per query (best[] reset)
+  const int64_t nct = std::max<int64_t>(static_cast<int64_t>(ncols_pad) * t.kpad / (t.f32 ? 4 : 8), nq);
   hipLaunchKernelGGL(match_ct_kernel, dim3(static_cast<unsigned>((nct + 255) / 256)), dim3(256), 0, s, ca);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   MatchArgs a = {};
@@ -1442,7 +1463,7 @@ hipError_t match_launch(const ScanTable& t, const uint8_t* free8, int W, int H, 
   }
 #undef MCL_MATCH
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL(match_reduce_kernel, dim3(nq), dim3(kScanThreads), 0, s, a);
+  hipLaunchKernelGGL(match_reduce_kernel, dim3(nq, kReduceChunks), dim3(kScanThreads), 0, s, a);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   return hipMemcpyAsync(best_host, best, static_cast<size_t>(nq) * sizeof(uint64_t), hipMemcpyDeviceToHost, s);
 }
