@@ -48,6 +48,38 @@ def test_distance_is_exact_small(f32_ops):
     assert np.array_equal(d_gpu, d_ref)
 
 
+@pytest.mark.parametrize("n_theta", [5, 72, 96, 120, 360])
+def test_distance_is_exact_at_depth_384(n_theta):
+    # 360 directions (depth 384), from a few channels to 360 (several passes
+    # over channel blocks); the distance output streams the circulant operand
+    occ = bsp_rooms(48, 37, seed=35)
+    R, m, f = _setup(occ, 0.1, 360, 4.0, n_theta, theta0=0.9)
+    rng = np.random.default_rng(36)
+    z = rng.uniform(0.0, 4.2, 360).astype(np.float32)
+    say(f"[scan] exact D depth 384 n_theta={n_theta}")
+    d_gpu = f.scan_sqdist(z).cpu().numpy().astype(np.int64).reshape(n_theta, -1)
+    Rq = O.quantize_ranges(R, 4.0)
+    zq = O.quantize_ranges(z, 4.0)
+    cells = rng.choice(48 * 37, 400, replace=False)
+    d_ref = O.scan_sqdist(Rq, zq, O.beam_offsets(0.9, n_theta, 360), rows=cells)
+    assert np.array_equal(d_gpu[:, cells], d_ref)
+
+
+@pytest.mark.parametrize("n_theta", [72, 120])
+def test_scan_update_at_depth_384_matches_oracle(n_theta):
+    # the likelihood pass on both operand paths of the BF16 product: up to 96
+    # channels the circulant operand is staged in LDS, above that it is streamed
+    occ = bsp_rooms(40, 30, seed=37)
+    R, m, f = _setup(occ, 0.1, 360, 4.0, n_theta, sxy=0.8, sth=0.8)
+    z = noisy_scan(occ, 0.1, (1.55, 1.45, 0.3), 360, 4.0, 0.1, seed=38)
+    say(f"[scan] update depth 384 n_theta={n_theta}")
+    f.apply_scan(z, 0.1)
+    b_gpu, _, _, _ = f.read_belief()
+    st = O.init_uniform(occ, n_theta)
+    st = O.apply_scan(st, O.quantize_ranges(R, 4.0), O.quantize_ranges(z, 4.0), 0.1, 4.0)
+    assert peak_err(b_gpu, st.B) <= SCAN_PEAK_TOL
+
+
 def test_distance_is_exact_full_size_sampled():
     # 512x512 cells, 360 directions, 72 channels: the GEMM shape of the scan workload
     occ = rooms_and_corridors(512, 512, seed=3)
