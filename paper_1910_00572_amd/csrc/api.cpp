@@ -820,6 +820,7 @@ mcl_status mcl_dither(const float* dev_intensity, int32_t width, int32_t height,
 
 size_t mcl_match_workspace_bytes(mcl_map map, int32_t n_theta, int32_t batch) {
   if (!map || map->scan.n_dirs == 0 || n_theta < 1 || n_theta > kMaxTheta || batch < 1 || batch > 65536) return 0;
+  if (static_cast<int64_t>(map->pitch) * map->H >= (static_cast<int64_t>(1) << 30)) return 0;
   return match_workspace_bytes(map->scan, map->H * map->pitch, n_theta, batch);
 }
 

@@ -338,6 +338,10 @@ def best_match(map: Map, n_theta, ranges_m, batch=64, stream=None):
     import torch
     lib = load_library()
     z = np.ascontiguousarray(ranges_m, dtype=np.float32)
+    if map.n_dirs == 0:
+        raise MclError(ESTATE, "the map has no range table")
+    if z.ndim != 2 or z.shape[1] != map.n_dirs:
+        raise MclError(EINVAL, f"ranges must be (n_queries, {map.n_dirs}), got {z.shape}")
     n = z.shape[0]
     nbytes = lib.mcl_match_workspace_bytes(map.handle, int(n_theta), int(batch))
     if nbytes == 0:

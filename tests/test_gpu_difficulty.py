@@ -122,6 +122,9 @@ def test_best_match_edge_cases():
         with pytest.raises(mcl.MclError) as e:
             mcl.best_match(m, bad, z)
         assert e.value.status == mcl.EINVAL
+    with pytest.raises(mcl.MclError) as e:
+        mcl.best_match(m, 4, z[:, :63])  # one direction short of the table
+    assert e.value.status == mcl.EINVAL
     zn = z.copy()
     zn[0, 5] = np.nan
     with pytest.raises(mcl.MclError) as e:
@@ -145,6 +148,13 @@ def test_best_match_edge_cases():
     st = lib.mcl_best_match(m2.handle, 4, z.ctypes.data, 1, 8, out.ctypes.data, None, None, ws.data_ptr(),
                             need, None)
     assert st == mcl.ESTATE
+    # the batch size changes nothing: one query per batch, or every query in one batch
+    rng = np.random.default_rng(54)
+    zz = _queries(occ, R, 4.0, rng, 3, 1, 1, 0, seed=55)
+    one = mcl.best_match(m, 6, zz, batch=1)
+    allq = mcl.best_match(m, 6, zz, batch=64)
+    for x, y in zip(one, allq):
+        assert np.array_equal(x, y)
     # a map with no free cell: no candidate at all
     full = np.ones((20, 24), np.uint8)
     _, m3 = _map(full, 0.15, 64, 4.0)
