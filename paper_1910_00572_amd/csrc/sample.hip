@@ -48,6 +48,7 @@ struct DitherArgs {
   uint8_t* mask;        // H x W dense output, 1 = selected
   int32_t W, H;
   int32_t ring;         // rows of the error ring (power of two)
+  int32_t rstride;      // floats between ring rows: ring_cols(K), or one more (odd, no bank conflicts)
   int32_t phases;       // phases to run (a multiple of the prefetch depth)
   uint32_t cells;       // W * H
 };
@@ -69,6 +70,7 @@ __global__ __launch_bounds__(kDitherMaxThreads) void dither_kernel(DitherArgs a)
   const int t = threadIdx.x, nt = blockDim.x;
   const int W = a.W, H = a.H;
   const int rmask = a.ring - 1;
+  const int RS = a.rstride;
   const int span = nt * MAXA;        // rows between consecutive rows of one slot
   const int wrap = (K + 1) * span;   // columns a slot moves back when it takes its next row
   const float w7 = 7.f / 16.f, w3 = 3.f / 16.f, w5 = 5.f / 16.f, w1 = 1.f / 16.f;
@@ -80,7 +82,7 @@ __global__ __launch_bounds__(kDitherMaxThreads) void dither_kernel(DitherArgs a)
       a.mask, static_cast<short>(0), static_cast<int>(a.cells), 0x00020000);
   constexpr uint32_t kOut = 0x80000000u;  // at or past the end of both buffers
 
-  for (int x = t; x < a.ring * D; x += nt) ering[x] = 0.f;
+  for (int x = t; x < a.ring * RS; x += nt) ering[x] = 0.f;
 
   int row[MAXA], col[MAXA];    // current row and first column of the phase
   int prow[MAXA], pcol[MAXA];  // the same, PF phases ahead (loads in flight)
@@ -126,8 +128,8 @@ __global__ __launch_bounds__(kDitherMaxThreads) void dither_kernel(DitherArgs a)
       for (int s = 0; s < MAXA; ++s) {
         const int j = row[s], i0 = col[s];
         // row above, columns i0-1 .. i0+K (written in earlier phases)
-        const float* up = ering + ((j - 1) & rmask) * D;
-        float* me = ering + (j & rmask) * D;
+        const float* up = ering + ((j - 1) & rmask) * RS;
+        float* me = ering + (j & rmask) * RS;
         float ua[K + 2];
 #pragma unroll
         for (int c = 0; c < K + 2; ++c) ua[c] = up[(i0 - 1 + c) & (D - 1)];
@@ -268,7 +270,7 @@ __global__ __launch_bounds__(kSrcThreads) void dither_source_kernel(const void* 
 
 // Launch geometry of the dithering kernel for a W x H image.
 struct DitherPlan {
-  int K = 0, slots = 0, threads = 0, ring = 0;
+  int K = 0, slots = 0, threads = 0, ring = 0, rstride = 0;
   size_t lds = 0;
   bool ok = false;
 };
@@ -295,7 +297,15 @@ DitherPlan plan_for(int W, int H, int K) {
                                          1 + (static_cast<int64_t>(W) + K + K) / (K + 1));
   if (slots > kDitherMaxSlots || rows > (1 << 20)) return p;
   p.ring = next_pow2(static_cast<int>(rows));
-  p.lds = static_cast<size_t>(p.ring) * ring_cols(K) * sizeof(float);
+  // consecutive threads hold consecutive ring rows: an odd row stride puts
+  // their accesses on distinct banks (a power-of-two stride shares banks
+  // among every eighth lane); kept unpadded where the padding would not fit
+  p.rstride = ring_cols(K) + 1;
+  p.lds = static_cast<size_t>(p.ring) * p.rstride * sizeof(float);
+  if (p.lds > kDitherMaxLds) {
+    p.rstride = ring_cols(K);
+    p.lds = static_cast<size_t>(p.ring) * p.rstride * sizeof(float);
+  }
   p.slots = static_cast<int>(slots < 1 ? 1 : slots);
   p.threads = static_cast<int>(nt < 64 ? 64 : nt);
   p.ok = p.lds <= kDitherMaxLds;
@@ -341,6 +351,7 @@ hipError_t launch_dither(const float* src, int W, int H, uint8_t* mask, bool sca
   a.W = W;
   a.H = H;
   a.ring = p.ring;
+  a.rstride = p.rstride;
   a.cells = static_cast<uint32_t>(static_cast<int64_t>(W) * H);
   if (scaled) {
     // the belief map in src becomes the intensity, in place
