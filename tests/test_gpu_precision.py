@@ -43,6 +43,30 @@ def test_reduced_precision_long_run(storage):
     say(f"[precision] {storage} worst L1 over 200 steps {worst:.3e}")
 
 
+@pytest.mark.parametrize("storage", ["bf16", "f16"])
+def test_reduced_precision_anisotropic(storage):
+    # the anisotropic two-pass step stores the belief in 16 bits as well
+    occ = bsp_rooms(72, 60, seed=45)
+    odo = random_odometry(40, seed=46, max_step_m=0.12)
+    n_theta = 24
+    p = oracle_params(n_theta, 0.1, 1.1, 0.8, flags=3 | 32, sigma_lateral=0.5)
+    _, f = make_gpu(occ, 0.1, n_theta, 1.1, 0.8, flags=3 | 32, sigma_lateral=0.5, storage=storage)
+    st = O.init_uniform(occ, n_theta)
+    M = O.free_mask(occ)
+    worst = 0.0
+    for t, (u, v, w) in enumerate(odo):
+        f.step_odometry(u, v, w)
+        st = O.step(st, occ, p, u, v, w, M=M)
+        if t % 10 == 9:
+            b, pose, _, ln = f.read_belief()
+            l1 = l1_err(b, st.B)
+            worst = max(worst, l1)
+            assert l1 <= L1_TOL, f"{storage} step {t}: L1 {l1:.3e}"
+            assert in_tie_set(pose.as_tuple(), st.B, TIE_TAU), f"{storage} step {t}: argmax {pose.as_tuple()}"
+            assert abs(ln - st.log_norm) < 1e-2
+    say(f"[precision] anisotropic {storage} worst L1 over 40 steps {worst:.3e}")
+
+
 def test_fp16_normalize_keeps_range():
     # FP16 cannot hold a sum-one belief of 16k states; normalize peaks it at one
     occ = bsp_rooms(64, 64, seed=43)
