@@ -65,14 +65,15 @@ def test_distance_is_exact_at_depth_384(n_theta):
     assert np.array_equal(d_gpu[:, cells], d_ref)
 
 
-@pytest.mark.parametrize("n_theta", [72, 120])
-def test_scan_update_at_depth_384_matches_oracle(n_theta):
-    # the likelihood pass on both operand paths of the BF16 product: up to 96
-    # channels the circulant operand is staged in LDS, above that it is streamed
+@pytest.mark.parametrize("n_theta,f32_ops", [(72, False), (120, False), (72, True), (120, True)])
+def test_scan_update_at_depth_384_matches_oracle(n_theta, f32_ops):
+    # the likelihood pass at depth 384: with BF16 operands up to 96 channels
+    # stage the circulant operand in LDS and more stream it; FP32 operands
+    # always stream it
     occ = bsp_rooms(40, 30, seed=37)
-    R, m, f = _setup(occ, 0.1, 360, 4.0, n_theta, sxy=0.8, sth=0.8)
+    R, m, f = _setup(occ, 0.1, 360, 4.0, n_theta, sxy=0.8, sth=0.8, flags=3 | (8 if f32_ops else 0))
     z = noisy_scan(occ, 0.1, (1.55, 1.45, 0.3), 360, 4.0, 0.1, seed=38)
-    say(f"[scan] update depth 384 n_theta={n_theta}")
+    say(f"[scan] update depth 384 n_theta={n_theta} f32_ops={f32_ops}")
     f.apply_scan(z, 0.1)
     b_gpu, _, _, _ = f.read_belief()
     st = O.init_uniform(occ, n_theta)
