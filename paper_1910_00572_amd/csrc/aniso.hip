@@ -138,7 +138,7 @@ __global__ __launch_bounds__(kThThreads) void aniso_theta_kernel(AnisoArgs a) {
     const float fx = sfx[c], fy = sfy[c];
     const int cn = c + 1 == n ? 0 : c + 1;
     float vn[4];
-    if (e + 1 < total) fetch(cn, vn);
+    fetch(cn, vn);  // past the last channel this reads a valid plane and is discarded
     const float s = ((1.f - fx) * v[0] + fx * v[1]) * (1.f - fy) + ((1.f - fx) * v[2] + fx * v[3]) * fy;
 #pragma unroll
     for (int l = kMaxTaps - 1; l > 0; --l) ring[l] = ring[l - 1];
