@@ -391,8 +391,8 @@ def main():
                     "(mixed, scan, sampled, gate, aniso, difficulty, serving); default all")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on exactly one GPU: the filter step is a single-GPU kernel and this build "
-              "has no multi-GPU path (see DESIGN.md, sharding).", file=sys.stderr)
+        print("bench.py runs on exactly one GPU: the filter step is a single-GPU kernel and there is "
+              "no multi-GPU path (sharding is a design only).", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -4,7 +4,7 @@ TEST INFRASTRUCTURE ONLY (see the package docstring).
 
 For every free location p the paper takes the observation z there, finds the
 location p_hat whose observation matches z best, and counts the locations with
-||p - p_hat|| > C (C = 1 m) among the free ones.  Readings (listed in the design doc):
+||p - p_hat|| > C (C = 1 m) among the free ones.  Readings:
 
   * the observation at p is a range scan at heading 0 (the table row of p,
     plus noise where the caller adds it), quantised as the scan update does;

@@ -14,7 +14,7 @@ the passage of the paper it follows:
   free-space tensor.
 * Eq. (sensor update): renormalise so the belief sums to one.
 
-Readings where the paper is silent or ambiguous (all listed in the design doc):
+Readings where the paper is silent or ambiguous:
 isotropic xy noise (so the heading rotation of the covariance is a no-op and
 the kernel separates), sampled taps normalised to sum one with radius
 ceil(3 sigma), bilinear warp with zero outside the grid, the pre-step heading

@@ -5,7 +5,7 @@ TEST INFRASTRUCTURE ONLY (see the package docstring).
 Instead of comparing a scan against every state, the paper selects a subset
 of states that follows the belief map with Floyd-Steinberg error diffusion and
 applies eq. (sensor update) to that subset.  The paper gives no further
-detail; the readings taken here (listed in the design doc):
+detail; the readings taken here:
 
   * Intensity.  I(i, j) = min(1, N_s * m(i, j) / sum m), with m the belief map
     (max over headings, Sec. III-A last paragraph) and N_s the requested number

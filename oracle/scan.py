@@ -12,7 +12,7 @@ Gaussian range model:
 r being the expected range from the cell along a world direction, read from a
 table of N directions.  Ranges are quantised to h = max_range / 256 on both
 sides, so the squared distance is an exact integer (the reading that keeps
-the dense form well conditioned; listed in the design doc).  The distance here is
+the dense form well conditioned).  The distance here is
 computed directly per beam, not through the expanded product form.
 """
 
