@@ -56,3 +56,34 @@ def l1_err(gpu_b, ref_b):
 def in_tie_set(pose_kji, ref_b, tau):
     k, j, i = pose_kji
     return bool(ref_b[k, j, i] >= ref_b.max() * (1.0 - tau))
+
+
+def stored_belief(f):
+    """The filter's stored belief as the kernels hold it (pitch layout,
+    storage type, scaled), widened to float64 and cut to (T, H, W).
+
+    Read with a plain device-to-host copy of mcl_info.belief_device, so a
+    test can start the oracle from exactly the values the GPU holds.
+    """
+    import ctypes
+    inf = f.info(sync=True)
+    eb = 4 if inf.storage == 0 else 2
+    n = inf.n_theta * inf.height * inf.pitch
+    raw = np.empty(n * eb, np.uint8)
+    hip = ctypes.CDLL("libamdhip64.so.7")
+    hip.hipMemcpy.restype = ctypes.c_int
+    hip.hipMemcpy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int]
+    rc = hip.hipMemcpy(raw.ctypes.data, inf.belief_device, n * eb, 2)  # device to host
+    assert rc == 0, f"hipMemcpy failed ({rc})"
+    if inf.storage == 0:
+        vals = raw.view(np.float32).astype(np.float64)
+    elif inf.storage == 1:
+        vals = (raw.view(np.uint16).astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+    else:
+        vals = raw.view(np.float16).astype(np.float64)
+    return vals.reshape(inf.n_theta, inf.height, inf.pitch)[:, :, :inf.width].copy()
+
+
+def oracle_state_from(stored, log_norm, theta):
+    """An oracle state holding the GPU's stored belief, renormalised in FP64."""
+    return O.FilterState(B=stored / stored.sum(), theta=theta, log_norm=log_norm)

@@ -3,12 +3,15 @@
 The squared distance D is an exact integer on both sides (quantised ranges,
 exact MFMA accumulation), so it is compared bit for bit, for BF16 and FP32
 matrix operands.  The posterior is compared with the oracle's log-domain
-update: peak-normalised max-abs error <= 2e-5 for FP32 storage.  That bound
-is derived from the FP32 arithmetic of the update: each stored value is
-exp(L - M*) with L - M* formed from two FP32 logarithms of values near the
-peak (abs. error ~1e-7 each) and c (D - D_ref) with |c (D - D_ref)| of tens
-of nats for the states that matter (relative error 6e-8, abs. ~3e-6), plus
-the FP32 exp (~1e-7): about 5e-6 relative per value, with a factor 4 margin.
+update: peak-normalised max-abs error <= 1e-5 for FP32 storage, the bound
+stated for FP32 results.  The FP32 arithmetic of the update stays well
+inside it: each stored value is exp(L - M*) with L - M* formed from FP32
+logarithms of values near the peak (abs. error ~1e-7 each) and
+c (D - D_ref) with D exact and |c (D - D_ref)| of a few nats for the states
+that carry mass (abs. error ~3e-7), plus the FP32 exp (~1e-7): about 5e-7
+relative per value.  The log-normaliser after a scan is checked against the
+oracle's scan started from the very FP32 prior the GPU holds, so the
+storage's precision does not enter the comparison.
 """
 
 import math
@@ -18,11 +21,14 @@ import pytest
 
 import oracle as O
 from gen import bsp_rooms, noisy_scan, random_odometry, range_table, rooms_and_corridors, smooth_trajectory
-from tests.gpu_harness import in_tie_set, make_gpu, needs_gpu, oracle_params, peak_err, say
+from tests.gpu_harness import (in_tie_set, make_gpu, needs_gpu, oracle_params, oracle_state_from, peak_err,
+                                say, stored_belief)
 
 pytestmark = [pytest.mark.gpu, needs_gpu]
 
-SCAN_PEAK_TOL = 2e-5
+SCAN_PEAK_TOL = 1e-5
+# the log-normaliser: absolute plus relative part
+LN_ABS, LN_REL = 1e-5, 1e-6
 
 
 def _setup(occ, cell, n_dirs, max_range, n_theta, sxy=0.7, sth=0.7, flags=3, theta0=0.0):
@@ -97,8 +103,10 @@ def test_distance_is_exact_full_size_sampled():
     assert np.array_equal(d_gpu[:, cells].astype(np.int64), d_ref)
 
 
-@pytest.mark.parametrize("f32_ops", [False, True])
-def test_scan_update_matches_oracle_with_motion(f32_ops):
+def _motion_and_scans(f32_ops, sigma_scan, seed_pose):
+    """30 odometry steps on a 64 x 56 plan with a 90-beam scan every 10 steps;
+    yields (t, GPU filter, oracle state, prior oracle state from the GPU's own
+    stored prior, quantised table, quantised scan) after each scan."""
     occ = bsp_rooms(64, 56, seed=34)
     n_theta = 16
     flags = 3 | (8 if f32_ops else 0)
@@ -108,7 +116,7 @@ def test_scan_update_matches_oracle_with_motion(f32_ops):
     st = O.init_uniform(occ, n_theta)
     odo = random_odometry(30, seed=35)
     free = np.argwhere(occ == 0)
-    rng = np.random.default_rng(36)
+    rng = np.random.default_rng(seed_pose)
     for t, (u, v, w) in enumerate(odo):
         f.step_odometry(u, v, w)
         st = O.step(st, occ, p, u, v, w)
@@ -116,24 +124,46 @@ def test_scan_update_matches_oracle_with_motion(f32_ops):
             j, i = free[rng.integers(len(free))]
             z = noisy_scan(occ, 0.1, ((i + 0.5) * 0.1, (j + 0.5) * 0.1, rng.uniform(-3, 3)), 90, 4.0, 0.1,
                            seed=t)
-            f.apply_scan(z, 0.1)
-            prior = st.B
-            st = O.apply_scan(st, Rq, O.quantize_ranges(z, 4.0), 0.1, 4.0)
-            b, pose, _, ln = f.read_belief()
-            err = peak_err(b, st.B)
-            # The log-normaliser of a scan is ln sum_q prior_q P(z|q); when the
-            # posterior is carried by a state whose prior is p_rel of the prior
-            # peak, FP32 storage (peak ~1) holds that prior to a relative
-            # precision of 2^-149 / p_rel once p_rel is below 2^-126 (denormal
-            # range), so the tolerance on ln grows by that much.
-            kq = np.unravel_index(int(np.argmax(st.B)), st.B.shape)
-            p_rel = prior[kq] / prior.max()
-            tol = 1e-5 + 1e-6 * abs(st.log_norm) + (4 * 2.0 ** -149 / p_rel if p_rel < 2.0 ** -126 else 0.0)
-            say(f"[scan] step {t} f32_ops={f32_ops} peak-normalised error {err:.3e} log_norm {ln:.6f} vs "
-                f"{st.log_norm:.6f} (prior at posterior argmax {p_rel:.3e} of peak, tol {tol:.2e})")
-            assert err <= SCAN_PEAK_TOL
-            assert in_tie_set(pose.as_tuple(), st.B, 1e-5)
-            assert abs(ln - st.log_norm) <= tol
+            _, _, th, ln_prior = f.read_belief(want_belief=False)
+            prior_gpu = oracle_state_from(stored_belief(f), ln_prior, th)
+            zq = O.quantize_ranges(z, 4.0)
+            f.apply_scan(z, sigma_scan)
+            st = O.apply_scan(st, Rq, zq, sigma_scan, 4.0)
+            yield t, f, st, O.apply_scan(prior_gpu, Rq, zq, sigma_scan, 4.0)
+
+
+@pytest.mark.parametrize("f32_ops", [False, True])
+def test_scan_update_matches_oracle_with_motion(f32_ops):
+    # a broad likelihood (sigma 1.5 m): the posterior keeps hundreds of states
+    # within 1e-3 of its peak, so the belief comparison is not one between two
+    # delta functions
+    for t, f, st, from_prior in _motion_and_scans(f32_ops, 1.5, 36):
+        b, pose, _, ln = f.read_belief()
+        err = peak_err(b, st.B)
+        near_peak = int((st.B > 1e-3 * st.B.max()).sum())
+        say(f"[scan] step {t} f32_ops={f32_ops} sigma 1.5: peak-normalised error {err:.3e}, {near_peak} states "
+            f"above 1e-3 of the peak, log_norm {ln:.8f} vs {from_prior.log_norm:.8f} (oracle from the GPU prior) "
+            f"and {st.log_norm:.8f} (oracle trajectory)")
+        assert near_peak >= 100
+        assert err <= SCAN_PEAK_TOL
+        assert peak_err(b, from_prior.B) <= SCAN_PEAK_TOL
+        assert in_tie_set(pose.as_tuple(), st.B, 1e-5)
+        assert abs(ln - from_prior.log_norm) <= LN_ABS + LN_REL * abs(from_prior.log_norm)
+        assert abs(ln - st.log_norm) <= LN_ABS + LN_REL * abs(st.log_norm)
+
+
+@pytest.mark.parametrize("f32_ops", [False, True])
+def test_sharp_scan_log_normaliser_from_the_gpu_prior(f32_ops):
+    # sigma 0.1 m: the posterior collapses onto a few states whose prior may
+    # be far below the prior's peak.  The log-normaliser is compared with the
+    # oracle's scan of the exact FP32 prior the GPU holds (no extra term).
+    for t, f, st, from_prior in _motion_and_scans(f32_ops, 0.1, 36):
+        b, pose, _, ln = f.read_belief()
+        say(f"[scan] step {t} f32_ops={f32_ops} sigma 0.1: log_norm {ln:.8f} vs {from_prior.log_norm:.8f} "
+            f"(oracle from the GPU prior), peak-normalised error {peak_err(b, from_prior.B):.3e}")
+        assert abs(ln - from_prior.log_norm) <= LN_ABS + LN_REL * abs(from_prior.log_norm)
+        assert peak_err(b, from_prior.B) <= SCAN_PEAK_TOL
+        assert in_tie_set(pose.as_tuple(), from_prior.B, 1e-5)
 
 
 def test_noise_free_scan_peaks_at_the_true_state():
