@@ -88,6 +88,13 @@ typedef struct {
   double sigma_lateral_cells;   /* MCL_ANISOTROPIC: noise std-dev across the heading, cells, > 0
                                    (sigma_xy_cells is then the std-dev along it, > 0; the 2-D
                                    kernel radius is radius_xy, or ceil(3 max(sf, sl)), at most 6) */
+  int32_t launch_shape[7];      /* testing and tuning only (filters; maps ignore it).  All zero:
+                                   the library chooses the step kernel's launch shape.  Otherwise
+                                   {tile width (0 = streaming kernel), rows per tile, threads per
+                                   workgroup, heading chunks (0 = automatic), source-row buffers
+                                   (streaming), variant (streaming: 0, 1 or 2), output strip
+                                   alignment in bytes (streaming; 0 = 32)}; init_belief fails with
+                                   EINVAL if no kernel has that shape */
 } mcl_params;
 
 typedef struct {
@@ -147,9 +154,12 @@ size_t mcl_filter_workspace_bytes(mcl_map map, const mcl_params* params);
 /* init_belief: create a filter on `map` (Sec. III-A, belief tensor).
  * init_host == NULL: B_0 uniform over the free cells of every heading channel.
  * Otherwise init_host is a host FP32 array of n_theta*H*W non-negative values
- * (any scale; it is renormalised) that becomes B_0 (checkpoint resume).
+ * (any scale; it is renormalised) that becomes B_0 (checkpoint resume); it is
+ * stored divided by its largest value, as the steps store the belief, so a
+ * sum-one export resumes in 16-bit storage without flushing small values.
  * theta0_rad sets the running heading offset.  sigma_xy / radius_xy / flags
- * must equal those the map was built with.  Synchronous. */
+ * must equal those the map was built with.  With init_host the call returns
+ * once the upload is done; the uniform start is only enqueued on `stream`. */
 mcl_status mcl_init_belief(mcl_map map, const mcl_params* params, void* dev_ws, size_t ws_bytes,
                            void* stream, const float* init_host, double theta0_rad,
                            mcl_filter* out);
@@ -173,6 +183,19 @@ mcl_status mcl_step_odometry(mcl_filter f, double u_m, double v_m, double w_rad)
  * n_beams must equal the map's n_dirs; ESTATE if the map has no range table. */
 mcl_status mcl_apply_scan(mcl_filter f, const float* ranges_m, int32_t n_beams, double sigma_m);
 
+/* apply_scan_batch (async, serving): mcl_apply_scan for n distinct filters
+ * of one map, driven on one stream.  ranges_m: host FP32, n scans of n_beams
+ * beams (filter i's at ranges_m[i * n_beams]); sigma_m: one std-dev per
+ * filter.  The cross-term products of all filters run in one launch in which
+ * every workgroup takes its tile of the range table for each filter in turn,
+ * so the table is read from memory once per launch instead of once per
+ * filter (up to 16 filters of one storage type and heading count per
+ * launch).  Each filter's result is bitwise that of mcl_apply_scan.  Errors
+ * as mcl_apply_scan for any filter; EINVAL for a repeated filter, filters of
+ * different maps or streams, or NULL pointers. */
+mcl_status mcl_apply_scan_batch(mcl_filter* const filters, const float* ranges_m, int32_t n_beams,
+                                const double* sigma_m, int32_t n);
+
 /* normalize (sync): rescale the stored belief in place so it sums to one
  * (FP32, BF16) or peaks at one (FP16, whose range cannot hold a sum-one
  * belief), and return the accumulated log-normaliser ln prod(kept mass)
@@ -192,6 +215,12 @@ mcl_status mcl_read_belief(mcl_filter f, float* host_out, mcl_pose* argmax,
  * (device, n_theta*H*W dense) and, if dev_map_out != NULL, the belief map
  * max_k B into dev_map_out (device, H*W). */
 mcl_status mcl_export_belief(mcl_filter f, float* dev_out, float* dev_map_out);
+
+/* export_scalars (async): dev_out (device, two doubles) receives the
+ * log-normaliser and the sticky status (as a double: 0 = MCL_OK, 3 =
+ * MCL_EDEGENERATE) as they stand after the work enqueued so far, so that a
+ * serving loop can retire a filter without synchronising the stream. */
+mcl_status mcl_export_scalars(mcl_filter f, double* dev_out);
 
 /* scan_sqdist (async, diagnostic): the exact integer squared distance
  * D[k][j][i] = sum_b (zq_b - rq(i, j, beam b of channel k))^2 between the
@@ -277,8 +306,9 @@ mcl_status mcl_difficulty(mcl_map map, const int32_t* query_cells, const int32_t
  * log_norm and status are current. */
 mcl_status mcl_get_info(mcl_filter f, int sync, mcl_info* out);
 
-/* Device bytes the batch job table of mcl_step_batch needs for up to
- * max_filters filters (0 if out of range). */
+/* Device bytes the batch job tables of mcl_step_batch (which uses the first
+ * half) and of mcl_batch_create (two parameter slots) need for up to
+ * max_filters filters per step (0 if out of range). */
 size_t mcl_batch_workspace_bytes(int32_t max_filters);
 
 /* step_batch (async, serving): one odometry step (as mcl_step_odometry) for
@@ -293,6 +323,38 @@ size_t mcl_batch_workspace_bytes(int32_t max_filters);
  * created on `stream` or be ordered with it by the caller. */
 mcl_status mcl_step_batch(mcl_filter* const filters, const double* uvw, int32_t n, void* dev_ws,
                           size_t ws_bytes, void* stream);
+
+/* ---- serving: graph-replayed batched steps ---------------------------------------- */
+typedef struct mcl_batch_s* mcl_batch;
+
+/* Create a batch runner on `stream` (a hipStream_t other than the default
+ * NULL stream, which cannot be captured) for up to max_filters filters per
+ * step (the continuous-batching pattern of the serving loop).
+ * dev_ws: caller-owned device memory of mcl_batch_workspace_bytes(max_filters)
+ * bytes, two parameter slots used in turn; the runner also allocates two
+ * pinned host slots of the same size (host memory, freed by destroy).  EINVAL
+ * for max_filters outside [1, 65536], NULL pointers or a NULL stream; ENOMEM
+ * for a small workspace; EDEVICE if the pinned allocation fails. */
+mcl_status mcl_batch_create(int32_t max_filters, void* dev_ws, size_t ws_bytes, void* stream, mcl_batch* out);
+
+/* batch_step: one odometry step for each of n distinct filters, the same
+ * work and the same bitwise results as mcl_step_batch, launched as a HIP
+ * graph: the host writes every filter's step parameters (job table with the
+ * odometry, per-channel shift tables) into a pinned slot; the graph copies
+ * the slot into device memory and runs one launch per kernel group, which
+ * read their parameters there.  Graphs are instantiated per launch structure
+ * (groups, job and workgroup counts) and replayed while it repeats, so
+ * filters joining or leaving cost one capture.  A slot is rewritten only after
+ * the replay that read it has completed (the call may wait for it).  The
+ * graphs hold no memset node.  Filters must be driven on the runner's stream.
+ * Errors as mcl_step_batch; EINVAL for n above max_filters. */
+mcl_status mcl_batch_step(mcl_batch b, mcl_filter* const filters, const double* uvw, int32_t n);
+
+/* Graph captures and replays of the runner so far (diagnostics). */
+mcl_status mcl_batch_counts(mcl_batch b, int64_t* captures, int64_t* replays);
+
+/* Waits for the runner's outstanding replays, then frees it. */
+void mcl_batch_destroy(mcl_batch b);
 
 #ifdef __cplusplus
 }

@@ -4,6 +4,7 @@
 // per-step scalars in FP64 (taps, heading bookkeeping, sub-cell gate) and
 // enqueues the kernels on the handle's stream.  No device allocation happens
 // here; all per-state arithmetic runs in the HIP kernels.
+#include <float.h>
 #include <math.h>
 #include <stdarg.h>
 #include <stdio.h>
@@ -91,6 +92,11 @@ mcl_status check_params(const mcl_params* p, bool need_theta) {
     const int rth = resolve_radius(p->sigma_theta_bins, p->radius_theta);
     if (rth > kMaxRadius) return fail(MCL_EINVAL, "theta blur radius %d exceeds %d", rth, kMaxRadius);
     if (p->storage < MCL_F32 || p->storage > MCL_F16) return fail(MCL_EINVAL, "unknown storage type");
+    for (int i = 0; i < 7; ++i)
+      if (p->launch_shape[i] < 0 || p->launch_shape[i] > 4096)
+        return fail(MCL_EINVAL, "launch_shape[%d] = %d out of range", i, p->launch_shape[i]);
+    const int al = p->launch_shape[6];
+    if (al != 0 && (al & (al - 1)) != 0) return fail(MCL_EINVAL, "strip alignment %d is not a power of two", al);
   }
   return MCL_OK;
 }
@@ -163,6 +169,9 @@ struct mcl_filter_s {
   double acc_x = 0.0, acc_y = 0.0;
   double rem[kMaxTheta][2] = {};  // carried remainders of the whole-cell warp, cells
   int32_t* ishift = nullptr;      // device: whole-cell shifts of the current warp
+  ShiftEntry* table_dev = nullptr;  // device: shift table of the current warp (heading counts above
+                                    // kArgTableMax; smaller tables travel in the kernel arguments)
+  ShiftEntry table[kMaxTheta] = {};  // host: shift table of the current warp
   float* aniso_tmp = nullptr;     // MCL_ANISOTROPIC: FP32 scratch of the theta-blurred tensor
   float* aniso_taps = nullptr;    // MCL_ANISOTROPIC: FP32 2-D taps per channel
   double sf = 0.0, sl = 0.0;      // MCL_ANISOTROPIC: std-devs along / across the heading
@@ -185,55 +194,47 @@ bool stream_plane_ok(int W, int H, size_t eb) {
   return pitch * static_cast<size_t>(H) * eb < (static_cast<size_t>(1) << 30);
 }
 
-// Launch shape of the step kernel, from measurements on MI355X.  Maps of
-// fewer than 512 64 x 16 tiles: streaming kernel, 4-row strips, 4 waves,
-// two slice buffers (512^2 x 72 FP32, one process: 52.8 us against 54.4 us
-// with 8-row strips, 61.0 us with 12-row strips, 56.9 us with 8-row strips
-// in two theta chunks and 62.3 us with 4-row strips in two; earlier, the tiled
-// kernel took 78.7 us).  Larger maps: streaming
-// kernel with 16-row strips, 8 waves and one slice buffer (1024^2 x 128:
-// FP32 332 us against 362 us tiled; BF16 278 us against 306-384 us for the
-// other streaming shapes).  The tiled kernel remains for planes of 1 GiB or
-// more, which the streaming kernel's 32-bit offsets cannot address.
-// MCL_STEP_SHAPE="tx,ty,nt[,chunks[,nbuf]]" overrides the choice (tx = 0:
-// streaming with nbuf source-slice buffers; chunks = 0: automatic).
-StepShape choose_shape(int W, int H, int T, int R, size_t eb) {
+// Launch shape of the step kernel, from measurements on MI355X (the numbers
+// below are per step; bench-style loops of 300 steps after a warm-up).  Maps
+// of fewer than 512 64 x 16 tiles: the variant-1 streaming kernel (mask in the
+// y taps, theta blur before the x blur, host shift table, emit pipelined
+// against the next warp), 4-row strips, 4 waves, two slice buffers, strips not
+// aligned beyond 4 bytes (512^2 x 72 FP32: 47.8 us against 52.6 us for the
+// variant-0 kernel at its best shape).  Larger maps: the variant-0 streaming
+// kernel with 16-row strips, 8 waves and one slice buffer (1024^2 x 128: FP32
+// 333 us with 32-byte aligned strips, BF16 241 us with 4-byte ones; the other
+// shapes and variants measured 247-379 us).  The tiled kernel remains for
+// planes of 1 GiB or more, which the streaming kernels' 32-bit offsets cannot
+// address.  A nonzero launch_shape in the parameters overrides the choice.
+StepShape choose_shape(int W, int H, int T, int R, size_t eb, const int32_t* force) {
   StepShape s;
   const int tiled_tiles = ((W + 63) / 64) * ((H + 15) / 16);
-  int sh[5] = {64, 16, 256, 0, 2};
+  int sh[7] = {64, 16, 256, 0, 2, 0, kStreamAlignBytes};
   if (stream_plane_ok(W, H, eb)) {
     if (tiled_tiles < 512) {
-      // four-row strips: twice the workgroups of eight-row strips (more waves
-      // per SIMD on small maps) at the cost of more halo rows per output
-      sh[0] = 0;
-      sh[1] = 4;
-      sh[2] = 256;
-      sh[3] = 1;
+      const int v[7] = {0, 4, 256, 1, 2, 1, 4};
+      for (int i = 0; i < 7; ++i) sh[i] = v[i];
     } else {
-      sh[0] = 0;
-      sh[1] = 16;
-      sh[2] = 512;
-      sh[3] = 1;
-      sh[4] = 1;
+      const int v[7] = {0, 16, 512, 1, 1, 0, eb == 4 ? 32 : 4};
+      for (int i = 0; i < 7; ++i) sh[i] = v[i];
     }
   }
-  if (const char* env = getenv("MCL_STEP_SHAPE")) {
-    int v[5] = {0, 0, 0, 0, 2};
-    if (sscanf(env, "%d,%d,%d,%d,%d", &v[0], &v[1], &v[2], &v[3], &v[4]) >= 3)
-      for (int i = 0; i < 5; ++i) sh[i] = v[i];
+  bool forced = false;
+  for (int i = 0; force && i < 7; ++i) forced = forced || force[i] != 0;
+  if (forced) {
+    for (int i = 0; i < 7; ++i) sh[i] = force[i];
+    if (sh[6] == 0) sh[6] = kStreamAlignBytes;
   }
   s.k.tx = sh[0];
   s.k.ty = sh[1];
   s.k.nt = sh[2];
   s.k.nbuf = sh[0] == 0 ? sh[4] : 2;
-  // streaming kernel: 32-byte aligned strips unless MCL_STREAM_ALIGN says otherwise
-  int align = kStreamAlignBytes;
-  if (const char* env = getenv("MCL_STREAM_ALIGN")) align = atoi(env);
-  s.strip = stream_strip_width(R, static_cast<int>(eb), align);
+  s.k.variant = sh[0] == 0 ? sh[5] : 0;
+  s.strip = stream_strip_width(R, static_cast<int>(eb), sh[6]);
   if (s.strip <= 0) s.strip = 63 - 2 * R;
   const int strip = s.k.tx > 0 ? s.k.tx : s.strip;
   s.tiles_x = (W + strip - 1) / strip;
-  s.tiles_y = (H + s.k.ty - 1) / s.k.ty;
+  s.tiles_y = (H + std::max(1, s.k.ty) - 1) / std::max(1, s.k.ty);
   const int tiles = s.tiles_x * s.tiles_y;
   int chunks = sh[3];
   if (chunks <= 0) {
@@ -307,12 +308,13 @@ size_t carve_filter(mcl_filter f, void* ws, const mcl_map m, const mcl_params* p
   void* b1 = c.take(n * eb);
   float* staging = static_cast<float*>(c.take(static_cast<size_t>(m->W) * m->H * sizeof(float)));
   const int R = std::max(1, std::max(m->rxy, resolve_radius(p->sigma_theta_bins, p->radius_theta)));
-  const StepShape sh = choose_shape(m->W, m->H, p->n_theta, R, eb);
+  const StepShape sh = choose_shape(m->W, m->H, p->n_theta, R, eb, p->launch_shape);
   int np = std::max(sh.blocks(), std::max(kReduceBlocks, kScanMaxBlocks(m->W, m->H, m->pitch)));
   if (p->flags & MCL_ANISOTROPIC) np = std::max(np, aniso_workgroups(m->W, m->H, p->n_theta));
   double* partials = static_cast<double*>(c.take(static_cast<size_t>(np) * 3 * sizeof(double)));
   FilterDev* dev = static_cast<FilterDev*>(c.take(kDevRegionBytes));
   int32_t* ishift = static_cast<int32_t*>(c.take(2 * kMaxTheta * sizeof(int32_t)));
+  ShiftEntry* table_dev = static_cast<ShiftEntry*>(c.take(kMaxTheta * sizeof(ShiftEntry)));
   float* atmp = (p->flags & MCL_ANISOTROPIC) ? static_cast<float*>(c.take(n * sizeof(float))) : nullptr;
   constexpr int kAnisoTaps = (2 * kAnisoMaxRadius + 1) * (2 * kAnisoMaxRadius + 1);
   float* ataps = (p->flags & MCL_ANISOTROPIC)
@@ -335,6 +337,7 @@ size_t carve_filter(mcl_filter f, void* ws, const mcl_map m, const mcl_params* p
     f->scan_scratch = scratch;
     f->samp_list = samp;
     f->ishift = ishift;
+    f->table_dev = table_dev;
     f->aniso_tmp = atmp;
     f->aniso_taps = ataps;
     f->scanw = scan_work_carve(scanw, p->n_theta, m->scan.kpad);
@@ -445,12 +448,14 @@ mcl_status mcl_init_belief(mcl_map map, const mcl_params* p, void* ws, size_t ws
   const size_t need = carve_filter(nullptr, nullptr, map, p);
   if (ws_bytes < need) return fail(MCL_ENOMEM, "filter workspace needs %zu bytes, got %zu", need, ws_bytes);
   const int64_t plane = static_cast<int64_t>(map->W) * map->H;
+  float init_max = 0.f;
   if (init_host) {
     double tot = 0.0;
     for (int64_t i = 0, n = plane * p->n_theta; i < n; ++i) {
       const float v = init_host[i];
       if (!(v >= 0.0f) || !isfinite(v)) return fail(MCL_EINVAL, "init belief has a negative or non-finite value");
       tot += v;
+      init_max = std::max(init_max, v);
     }
     if (!(tot > 0.0)) return fail(MCL_EINVAL, "init belief has no mass");
   } else if (map->n_free == 0) {
@@ -491,13 +496,17 @@ mcl_status mcl_init_belief(mcl_map map, const mcl_params* p, void* ws, size_t ws
       e = launch_dev_init(f->dev, static_cast<double>(map->n_free) * f->T, 1.0f, f->stream);
   } else {
     const size_t eb = dtype_bytes(f->dtype);
+    const double inv = 1.0 / static_cast<double>(init_max);
+    const float init_scale = inv > static_cast<double>(FLT_MAX) ? FLT_MAX : static_cast<float>(inv);
     e = hipMemsetAsync(f->buf[1], 0, static_cast<size_t>(f->sstride) * f->T * eb, f->stream);
     for (int k = 0; k < f->T && e == hipSuccess; ++k) {
       e = hipMemcpyAsync(f->staging, init_host + k * plane, plane * sizeof(float), hipMemcpyHostToDevice,
                          f->stream);
+      // stored max-scaled (peak one), as every step stores it: a sum-one
+      // belief of many states lies below the 16-bit types' smallest values
       if (e == hipSuccess)
         e = launch_slice_from_f32(f->dtype, f->staging, static_cast<char*>(f->buf[0]) + k * f->sstride * eb,
-                                  map->W, map->H, map->pitch, f->stream);
+                                  map->W, map->H, map->pitch, init_scale, f->stream);
     }
     if (e == hipSuccess) e = launch_dev_init(f->dev, 1.0, 1.0f, f->stream);
     if (e == hipSuccess) {
@@ -505,7 +514,9 @@ mcl_status mcl_init_belief(mcl_map map, const mcl_params* p, void* ws, size_t ws
       e = launch_reduce(f->dtype, r, kReduceBlocks, f->stream);
     }
   }
-  if (e == hipSuccess) e = hipStreamSynchronize(f->stream);
+  // the upload of a host belief waits for its copies; the uniform start only
+  // enqueues (device errors surface at the next synchronising call)
+  if (e == hipSuccess && init_host) e = hipStreamSynchronize(f->stream);
   if (e != hipSuccess) {
     delete f;
     return hip_fail(e, "init_belief");
@@ -517,13 +528,16 @@ mcl_status mcl_init_belief(mcl_map map, const mcl_params* p, void* ws, size_t ws
 void mcl_filter_destroy(mcl_filter f) { delete f; }
 
 // Host bookkeeping of one odometry step (Sec. III-A-1, Alg. 1): the heading
-// offset, the sub-cell gate's accumulated displacement and, with
-// MCL_INTEGER_SHIFT, the per-channel whole-cell shifts and carried remainders
-// (written to the device on stream s).  *launch says whether a warp happens.
-// The arithmetic is FP64 in the order of the displacement formula
-// R(psi_k) [u, v] / cell with psi_k = theta + k 2 pi / n_theta.
+// offset, the sub-cell gate's accumulated displacement, the per-channel shift
+// table f->table (FP64 displacement R(psi_k) [u, v] / cell split into whole
+// cells and a bilinear fraction; with MCL_INTEGER_SHIFT the whole-cell shifts
+// with their carried remainders and zero fractions) and, for kernels that read
+// it from device memory, the whole-cell list (written on stream s when
+// dev_ishift is set).  *launch says whether a warp happens.  The arithmetic is
+// FP64 in the order of the displacement formula with psi_k = theta + k 2 pi /
+// n_theta.
 static hipError_t plan_motion(mcl_filter f, double u, double v, double w, StepArgs& a, hipStream_t s,
-                              bool* launch) {
+                              bool* launch, bool dev_ishift) {
   const double cell = f->map->cell;
   const uint32_t flags = f->map->flags;
   double mu = u, mv = v, th = f->theta;  // motion to warp by and the heading it is expressed at
@@ -552,9 +566,10 @@ static hipError_t plan_motion(mcl_filter f, double u, double v, double w, StepAr
   a.v_cells = mv / cell;
   a.theta_prev = th;
   a.ishift = nullptr;
+  a.table = nullptr;
+  const double dth = 2.0 * M_PI / f->T;
   if (flags & MCL_INTEGER_SHIFT) {
     int32_t n[2 * kMaxTheta];
-    const double dth = 2.0 * M_PI / f->T;
     for (int k = 0; k < f->T; ++k) {
       const double psi = th + k * dth;
       const double c = cos(psi), sn = sin(psi);
@@ -565,12 +580,44 @@ static hipError_t plan_motion(mcl_filter f, double u, double v, double w, StepAr
       f->rem[k][1] = dy - ny;
       n[2 * k] = static_cast<int32_t>(nx);
       n[2 * k + 1] = static_cast<int32_t>(ny);
+      f->table[k] = ShiftEntry{n[2 * k], n[2 * k + 1], 0.f, 0.f};
     }
-    const hipError_t e = launch_write_shifts(n, f->T, f->ishift, s);
-    if (e != hipSuccess) return e;
-    a.ishift = f->ishift;
+    if (dev_ishift) {
+      const hipError_t e = launch_write_shifts(n, f->T, f->ishift, s);
+      if (e != hipSuccess) return e;
+      a.ishift = f->ishift;
+    }
+    return hipSuccess;
+  }
+  // the bilinear warp: floor and fraction of the displacement in cells
+  const double uc = a.u_cells, vc = a.v_cells;
+  for (int k = 0; k < f->T; ++k) {
+    const double psi = th + k * dth;
+    const double c = cos(psi), sn = sin(psi);
+    const double dx = uc * c - vc * sn;
+    const double dy = uc * sn + vc * c;
+    const double fdx = floor(dx), fdy = floor(dy);
+    f->table[k] = ShiftEntry{static_cast<int32_t>(fdx), static_cast<int32_t>(fdy), static_cast<float>(dx - fdx),
+                             static_cast<float>(dy - fdy)};
   }
   return hipSuccess;
+}
+
+// Launch the fused step of one filter: variant-1 streaming kernels take the
+// shift table from the kernel arguments (or, above kArgTableMax channels,
+// from the filter's device table, written here through kernel arguments).
+static hipError_t launch_filter_step(mcl_filter f, StepArgs& a) {
+  if (f->shape.k.variant == 0) return launch_step(f->dtype, f->radius, f->shape.k, a, nullptr, f->stream);
+  if (f->T <= kArgTableMax) {
+    ShiftArgs tab;
+    memcpy(tab.e, f->table, static_cast<size_t>(f->T) * sizeof(ShiftEntry));
+    a.table = nullptr;
+    return launch_step(f->dtype, f->radius, f->shape.k, a, &tab, f->stream);
+  }
+  const hipError_t e = launch_write_table(f->table, f->T, f->table_dev, f->stream);
+  if (e != hipSuccess) return e;
+  a.table = f->table_dev;
+  return launch_step(f->dtype, f->radius, f->shape.k, a, nullptr, f->stream);
 }
 
 // Arguments of the anisotropic step from the fused step's (motion, buffers)
@@ -615,13 +662,14 @@ mcl_status mcl_step_odometry(mcl_filter f, double u, double v, double w) {
   StepArgs a = make_step_args(f);
   bool launch = false;
   const double theta_pre = f->theta;
-  HIP_TRY(plan_motion(f, u, v, w, a, f->stream, &launch), "shift table");
+  const bool aniso = (f->map->flags & MCL_ANISOTROPIC) != 0;
+  HIP_TRY(plan_motion(f, u, v, w, a, f->stream, &launch, aniso || f->shape.k.variant == 0), "shift table");
   if (!launch) return MCL_OK;
-  if (f->map->flags & MCL_ANISOTROPIC) {
+  if (aniso) {
     HIP_TRY(launch_aniso_step(f->dtype, make_aniso_args(f, a, theta_pre), f->stream), "step launch");
     return MCL_OK;
   }
-  HIP_TRY(launch_step(f->dtype, f->radius, f->shape.k, a, f->stream), "step launch");
+  HIP_TRY(launch_filter_step(f, a), "step launch");
   return MCL_OK;
 }
 
@@ -653,6 +701,12 @@ mcl_status mcl_export_belief(mcl_filter f, float* dev_out, float* dev_map_out) {
   HIP_TRY(launch_export(f->dtype, f->buf[d.cur], m->W, m->H, m->pitch, f->T, f->sstride, f->dev, dev_out,
                         static_cast<int64_t>(m->W) * m->H, 0, dev_out ? f->T : 0, dev_map_out, f->stream),
           "export");
+  return MCL_OK;
+}
+
+mcl_status mcl_export_scalars(mcl_filter f, double* dev_out) {
+  if (!f || !dev_out) return fail(MCL_EINVAL, "filter or output is NULL");
+  HIP_TRY(launch_export_scalars(f->dev, dev_out, f->stream), "export scalars");
   return MCL_OK;
 }
 
@@ -770,6 +824,26 @@ static mcl_status scan_common(mcl_filter f, const float* ranges_m, int32_t n_bea
 
 mcl_status mcl_apply_scan(mcl_filter f, const float* ranges_m, int32_t n_beams, double sigma_m) {
   return scan_common(f, ranges_m, n_beams, sigma_m, nullptr);
+}
+
+mcl_status mcl_apply_scan_batch(mcl_filter* const filters, const float* ranges_m, int32_t n_beams,
+                                const double* sigma_m, int32_t n) {
+  if (!filters || !ranges_m || !sigma_m || n < 1 || n > 65536)
+    return fail(MCL_EINVAL, "filters/ranges/sigma NULL or n out of range");
+  std::vector<ScanLaunch> Ls;
+  Ls.reserve(n);
+  for (int i = 0; i < n; ++i) {
+    mcl_filter f = filters[i];
+    const mcl_status st = scan_check(f, ranges_m + static_cast<int64_t>(i) * n_beams, n_beams, sigma_m[i], true);
+    if (st != MCL_OK) return st;
+    for (int j = 0; j < i; ++j)
+      if (filters[j] == f) return fail(MCL_EINVAL, "filter %d appears twice", i);
+    if (f->map != filters[0]->map) return fail(MCL_EINVAL, "filter %d is on another map", i);
+    if (f->stream != filters[0]->stream) return fail(MCL_EINVAL, "filter %d is on another stream", i);
+    Ls.push_back(scan_args(f));
+  }
+  HIP_TRY(scan_launch_batch(Ls.data(), n, ranges_m, sigma_m), "scan batch launch");
+  return MCL_OK;
 }
 
 mcl_status mcl_scan_sqdist(mcl_filter f, const float* ranges_m, int32_t n_beams, int32_t* dev_out) {
@@ -938,23 +1012,30 @@ mcl_status mcl_difficulty(mcl_map map, const int32_t* query_cells, const int32_t
   return MCL_OK;
 }
 
-static size_t batch_bytes(int32_t n) {
-  Carver c(nullptr);
-  c.take(static_cast<size_t>(n) * sizeof(StepArgs));
-  c.take(static_cast<size_t>(2 * n + 2) * sizeof(int32_t));
-  return c.off;
+// One batch parameter slot, the same layout on the host and the device: the
+// job table, the first-workgroup offsets of every group and the jobs' shift
+// tables.
+struct SlotLayout {
+  size_t args_off = 0, first_off = 0, tables_off = 0, bytes = 0;
+};
+static SlotLayout slot_layout(int32_t n) {
+  auto up = [](size_t x) { return (x + 255) & ~static_cast<size_t>(255); };
+  SlotLayout l;
+  l.args_off = 0;
+  l.first_off = up(static_cast<size_t>(n) * sizeof(StepArgs));
+  l.tables_off = up(l.first_off + static_cast<size_t>(2 * n + 2) * sizeof(int32_t));
+  l.bytes = up(l.tables_off + static_cast<size_t>(n) * kMaxTheta * sizeof(ShiftEntry));
+  return l;
 }
 
-size_t mcl_batch_workspace_bytes(int32_t max_filters) {
-  if (max_filters < 1 || max_filters > 65536) return 0;
-  return batch_bytes(max_filters);
-}
+struct BatchGroup {
+  int dtype, radius;
+  KernelShape k;
+  int job0, first0, njobs, blocks, max_theta;
+};
 
-mcl_status mcl_step_batch(mcl_filter* const filters, const double* uvw, int32_t n, void* dev_ws, size_t ws_bytes,
-                          void* stream) {
+static mcl_status check_batch(mcl_filter* const filters, const double* uvw, int32_t n) {
   if (!filters || !uvw || n < 1 || n > 65536) return fail(MCL_EINVAL, "filters/uvw NULL or n out of range");
-  if (!dev_ws) return fail(MCL_EINVAL, "workspace is NULL");
-  if (ws_bytes < batch_bytes(n)) return fail(MCL_ENOMEM, "batch workspace needs %zu bytes", batch_bytes(n));
   for (int i = 0; i < n; ++i) {
     if (!filters[i]) return fail(MCL_EINVAL, "filter %d is NULL", i);
     for (int j = 0; j < i; ++j)
@@ -964,77 +1045,235 @@ mcl_status mcl_step_batch(mcl_filter* const filters, const double* uvw, int32_t 
     const double cell = filters[i]->map->cell;
     if (fabs(o[0]) / cell > 1e6 || fabs(o[1]) / cell > 1e6) return fail(MCL_EINVAL, "odometry %d too large", i);
   }
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  // Host bookkeeping identical to mcl_step_odometry; a filter whose sub-cell
-  // gate does not fire takes no launch.
+  return MCL_OK;
+}
+
+// Host side of one batched step: each filter's bookkeeping as in
+// mcl_step_odometry (a filter whose sub-cell gate does not fire takes no
+// launch; anisotropic filters launch their own passes on s), then the job
+// table, offsets and shift tables written into `host` (laid out as
+// slot_layout(n)) with device pointers into `dev`.  *used = bytes to copy.
+static mcl_status plan_batch(mcl_filter* const filters, const double* uvw, int32_t n, hipStream_t s, char* host,
+                             char* dev, std::vector<BatchGroup>& groups, size_t* used) {
   struct Job {
     StepArgs a;
     int dtype, radius;
     KernelShape k;
+    mcl_filter f;
   };
   std::vector<Job> jobs;
   jobs.reserve(n);
   for (int i = 0; i < n; ++i) {
     mcl_filter f = filters[i];
     const double u = uvw[3 * i], v = uvw[3 * i + 1], w = uvw[3 * i + 2];
-    const double cell = f->map->cell;
     StepArgs a = make_step_args(f);
     bool launch = false;
     const double theta_pre = f->theta;
-    HIP_TRY(plan_motion(f, u, v, w, a, static_cast<hipStream_t>(stream), &launch), "shift table");
+    const bool aniso = (f->map->flags & MCL_ANISOTROPIC) != 0;
+    HIP_TRY(plan_motion(f, u, v, w, a, s, &launch, aniso || f->shape.k.variant == 0), "shift table");
     if (!launch) continue;
-    if (f->map->flags & MCL_ANISOTROPIC) {
-      // two plain passes of its own, on the batch stream
-      HIP_TRY(launch_aniso_step(f->dtype, make_aniso_args(f, a, theta_pre), static_cast<hipStream_t>(stream)),
-              "step launch");
+    if (aniso) {
+      HIP_TRY(launch_aniso_step(f->dtype, make_aniso_args(f, a, theta_pre), s), "step launch");
       continue;
     }
-    jobs.push_back(Job{a, f->dtype, f->radius, f->shape.k});
+    jobs.push_back(Job{a, f->dtype, f->radius, f->shape.k, f});
   }
+  groups.clear();
+  *used = 0;
   if (jobs.empty()) return MCL_OK;
-  auto same = [](const Job& x, const Job& y) {
-    return x.dtype == y.dtype && x.radius == y.radius && x.k == y.k;
-  };
+  auto same = [](const Job& x, const Job& y) { return x.dtype == y.dtype && x.radius == y.radius && x.k == y.k; };
   auto less = [](const Job& x, const Job& y) {
     if (x.dtype != y.dtype) return x.dtype < y.dtype;
     if (x.radius != y.radius) return x.radius < y.radius;
     return x.k < y.k;
   };
   std::stable_sort(jobs.begin(), jobs.end(), less);
-  // per group: its jobs, then njobs+1 first-block offsets relative to the group
-  std::vector<StepArgs> args;
-  std::vector<int32_t> first;
-  struct Group {
-    int dtype, radius;
-    KernelShape k;
-    int job0, first0, njobs, blocks, max_theta;
-  };
-  std::vector<Group> groups;
+  const SlotLayout lay = slot_layout(n);
+  StepArgs* args = reinterpret_cast<StepArgs*>(host + lay.args_off);
+  int32_t* first = reinterpret_cast<int32_t*>(host + lay.first_off);
+  ShiftEntry* tables = reinterpret_cast<ShiftEntry*>(host + lay.tables_off);
+  const ShiftEntry* tables_dev = reinterpret_cast<const ShiftEntry*>(dev + lay.tables_off);
+  int nfirst = 0, ntab = 0;
   for (size_t i = 0; i < jobs.size(); ++i) {
     if (i == 0 || !same(jobs[i], jobs[i - 1])) {
-      if (!groups.empty()) first.push_back(groups.back().blocks);
-      groups.push_back(Group{jobs[i].dtype, jobs[i].radius, jobs[i].k,
-                             static_cast<int>(args.size()), static_cast<int>(first.size()), 0, 0, 0});
+      if (!groups.empty()) first[nfirst++] = groups.back().blocks;
+      groups.push_back(BatchGroup{jobs[i].dtype, jobs[i].radius, jobs[i].k, static_cast<int>(i), nfirst, 0, 0, 0});
     }
-    Group& g = groups.back();
-    first.push_back(g.blocks);
-    args.push_back(jobs[i].a);
+    BatchGroup& g = groups.back();
+    first[nfirst++] = g.blocks;
+    args[i] = jobs[i].a;
+    if (jobs[i].k.variant != 0) {
+      // variant-1/2 kernels read the job's shift table from the slot
+      args[i].table = tables_dev + ntab;
+      memcpy(tables + ntab, jobs[i].f->table, static_cast<size_t>(jobs[i].f->T) * sizeof(ShiftEntry));
+      ntab += jobs[i].f->T;
+    }
     g.blocks += jobs[i].a.tiles_x * jobs[i].a.tiles_y * jobs[i].a.chunks;
     g.max_theta = std::max(g.max_theta, static_cast<int>(jobs[i].a.n_theta));
     ++g.njobs;
   }
-  first.push_back(groups.back().blocks);
-  Carver c(dev_ws);
-  StepArgs* args_dev = static_cast<StepArgs*>(c.take(args.size() * sizeof(StepArgs)));
-  int32_t* first_dev = static_cast<int32_t*>(c.take(first.size() * sizeof(int32_t)));
-  HIP_TRY(hipMemcpyAsync(args_dev, args.data(), args.size() * sizeof(StepArgs), hipMemcpyHostToDevice, s),
-          "batch jobs upload");
-  HIP_TRY(hipMemcpyAsync(first_dev, first.data(), first.size() * sizeof(int32_t), hipMemcpyHostToDevice, s),
-          "batch offsets upload");
-  for (const Group& g : groups)
-    HIP_TRY(launch_step_batch(g.dtype, g.radius, g.k, args_dev + g.job0, first_dev + g.first0, g.njobs, g.blocks,
-                              g.max_theta, s),
-            "batch launch");
+  first[nfirst++] = groups.back().blocks;
+  *used = lay.tables_off + static_cast<size_t>(ntab) * sizeof(ShiftEntry);
+  return MCL_OK;
+}
+
+static hipError_t launch_groups(const std::vector<BatchGroup>& groups, char* dev, int32_t n, hipStream_t s) {
+  const SlotLayout lay = slot_layout(n);
+  const StepArgs* args_dev = reinterpret_cast<const StepArgs*>(dev + lay.args_off);
+  const int32_t* first_dev = reinterpret_cast<const int32_t*>(dev + lay.first_off);
+  for (const BatchGroup& g : groups) {
+    const hipError_t e = launch_step_batch(g.dtype, g.radius, g.k, args_dev + g.job0, first_dev + g.first0, g.njobs,
+                                           g.blocks, g.max_theta, s);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+size_t mcl_batch_workspace_bytes(int32_t max_filters) {
+  if (max_filters < 1 || max_filters > 65536) return 0;
+  return 2 * slot_layout(max_filters).bytes;
+}
+
+mcl_status mcl_step_batch(mcl_filter* const filters, const double* uvw, int32_t n, void* dev_ws, size_t ws_bytes,
+                          void* stream) {
+  mcl_status st = check_batch(filters, uvw, n);
+  if (st != MCL_OK) return st;
+  if (!dev_ws) return fail(MCL_EINVAL, "workspace is NULL");
+  const SlotLayout lay = slot_layout(n);
+  if (ws_bytes < lay.bytes) return fail(MCL_ENOMEM, "batch workspace needs %zu bytes", lay.bytes);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  std::vector<char> host(lay.bytes);
+  std::vector<BatchGroup> groups;
+  size_t used = 0;
+  char* dev = static_cast<char*>(dev_ws);
+  if ((st = plan_batch(filters, uvw, n, s, host.data(), dev, groups, &used)) != MCL_OK) return st;
+  if (groups.empty()) return MCL_OK;
+  // a copy from pageable memory: the host buffer may be released on return
+  HIP_TRY(hipMemcpyAsync(dev, host.data(), used, hipMemcpyHostToDevice, s), "batch jobs upload");
+  HIP_TRY(launch_groups(groups, dev, n, s), "batch launch");
+  return MCL_OK;
+}
+
+}  // extern "C"
+
+// ---- graph-replayed batches (serving) ------------------------------------------------
+struct mcl_batch_s {
+  int32_t max_filters = 0;
+  hipStream_t stream = nullptr;
+  SlotLayout lay;
+  char* dev[2] = {nullptr, nullptr};   // device parameter slots (caller's workspace)
+  char* host[2] = {nullptr, nullptr};  // pinned host parameter slots
+  hipEvent_t done[2] = {nullptr, nullptr};
+  bool pending[2] = {false, false};
+  int next = 0;
+  struct Graph {
+    std::vector<int64_t> key;
+    hipGraphExec_t exec = nullptr;
+  };
+  std::vector<Graph> graphs[2];
+  int64_t captures = 0, replays = 0;
+  ~mcl_batch_s() {
+    for (int i = 0; i < 2; ++i) {
+      for (Graph& g : graphs[i])
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+      if (done[i]) (void)hipEventDestroy(done[i]);
+      if (host[i]) (void)hipHostFree(host[i]);
+    }
+  }
+};
+
+namespace {
+constexpr size_t kBatchGraphCache = 32;  // instantiated graphs kept per slot
+}
+
+extern "C" {
+
+mcl_status mcl_batch_create(int32_t max_filters, void* dev_ws, size_t ws_bytes, void* stream, mcl_batch* out) {
+  if (!out) return fail(MCL_EINVAL, "out is NULL");
+  const size_t need = mcl_batch_workspace_bytes(max_filters);
+  if (need == 0) return fail(MCL_EINVAL, "max_filters out of range");
+  if (!dev_ws) return fail(MCL_EINVAL, "workspace is NULL");
+  if (!stream) return fail(MCL_EINVAL, "graph capture needs a stream other than the default (NULL) stream");
+  if (ws_bytes < need) return fail(MCL_ENOMEM, "batch workspace needs %zu bytes, got %zu", need, ws_bytes);
+  mcl_batch b = new mcl_batch_s();
+  b->max_filters = max_filters;
+  b->stream = static_cast<hipStream_t>(stream);
+  b->lay = slot_layout(max_filters);
+  for (int i = 0; i < 2; ++i) {
+    b->dev[i] = static_cast<char*>(dev_ws) + i * b->lay.bytes;
+    hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&b->host[i]), b->lay.bytes, hipHostMallocDefault);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&b->done[i], hipEventDisableTiming);
+    if (e != hipSuccess) {
+      delete b;
+      return hip_fail(e, "batch slots");
+    }
+  }
+  *out = b;
+  return MCL_OK;
+}
+
+void mcl_batch_destroy(mcl_batch b) {
+  if (!b) return;
+  for (int i = 0; i < 2; ++i)
+    if (b->pending[i]) (void)hipEventSynchronize(b->done[i]);
+  delete b;
+}
+
+mcl_status mcl_batch_step(mcl_batch b, mcl_filter* const filters, const double* uvw, int32_t n) {
+  if (!b) return fail(MCL_EINVAL, "batch is NULL");
+  mcl_status st = check_batch(filters, uvw, n);
+  if (st != MCL_OK) return st;
+  if (n > b->max_filters) return fail(MCL_EINVAL, "%d filters, the batch holds at most %d", n, b->max_filters);
+  const int slot = b->next;
+  // the slot's previous replay must have read its parameters
+  if (b->pending[slot]) HIP_TRY(hipEventSynchronize(b->done[slot]), "batch slot wait");
+  b->pending[slot] = false;
+  std::vector<BatchGroup> groups;
+  size_t used = 0;
+  if ((st = plan_batch(filters, uvw, n, b->stream, b->host[slot], b->dev[slot], groups, &used)) != MCL_OK) return st;
+  if (groups.empty()) return MCL_OK;
+  b->next ^= 1;
+  // the graph depends on the launch structure and the copied size, not on the
+  // parameters, which the copy node reads from the pinned slot at every replay
+  std::vector<int64_t> key = {n, static_cast<int64_t>(used)};
+  for (const BatchGroup& g : groups) {
+    const int64_t k[] = {g.dtype, g.radius, g.k.tx, g.k.ty, g.k.nt, g.k.nbuf, g.k.variant, g.job0, g.first0,
+                         g.njobs, g.blocks, g.max_theta};
+    key.insert(key.end(), k, k + 12);
+  }
+  std::vector<mcl_batch_s::Graph>& cache = b->graphs[slot];
+  hipGraphExec_t exec = nullptr;
+  for (mcl_batch_s::Graph& g : cache)
+    if (g.key == key) exec = g.exec;
+  if (!exec) {
+    hipGraph_t graph = nullptr;
+    HIP_TRY(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal), "graph capture");
+    hipError_t e = hipMemcpyAsync(b->dev[slot], b->host[slot], used, hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess) e = launch_groups(groups, b->dev[slot], n, b->stream);
+    const hipError_t e2 = hipStreamEndCapture(b->stream, &graph);
+    if (e == hipSuccess) e = e2;
+    if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return hip_fail(e, "graph capture");
+    if (cache.size() >= kBatchGraphCache) {
+      // the oldest graph of this slot: its last replay was waited for above
+      (void)hipGraphExecDestroy(cache.front().exec);
+      cache.erase(cache.begin());
+    }
+    cache.push_back(mcl_batch_s::Graph{key, exec});
+    ++b->captures;
+  }
+  HIP_TRY(hipGraphLaunch(exec, b->stream), "graph launch");
+  HIP_TRY(hipEventRecord(b->done[slot], b->stream), "batch slot event");
+  b->pending[slot] = true;
+  ++b->replays;
+  return MCL_OK;
+}
+
+mcl_status mcl_batch_counts(mcl_batch b, int64_t* captures, int64_t* replays) {
+  if (!b) return fail(MCL_EINVAL, "batch is NULL");
+  if (captures) *captures = b->captures;
+  if (replays) *replays = b->replays;
   return MCL_OK;
 }
 

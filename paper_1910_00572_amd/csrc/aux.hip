@@ -72,11 +72,11 @@ __global__ void init_uniform_kernel(T* __restrict__ b0, T* __restrict__ b1, cons
 
 template <typename T>
 __global__ void slice_from_f32_kernel(const float* __restrict__ src, T* __restrict__ dst, int W, int H,
-                                      int pitch) {
+                                      int pitch, float factor) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int y = blockIdx.y;
   if (x >= pitch || y >= H) return;
-  const float v = x < W ? src[static_cast<int64_t>(y) * W + x] : 0.f;
+  const float v = x < W ? src[static_cast<int64_t>(y) * W + x] * factor : 0.f;
   dst[static_cast<int64_t>(y) * pitch + x] = static_cast<T>(v);
 }
 
@@ -235,6 +235,15 @@ __global__ void write_shifts_kernel(ShiftList l, int count, int32_t* __restrict_
   for (int i = threadIdx.x; i < 2 * count; i += blockDim.x) dst[i] = l.n[i];
 }
 
+__global__ void write_table_kernel(ShiftArgs t, int count, ShiftEntry* __restrict__ dst) {
+  for (int i = threadIdx.x; i < count; i += blockDim.x) dst[i] = t.e[i];
+}
+
+__global__ void export_scalars_kernel(const FilterDev* dev, double* out) {
+  out[0] = dev->log_norm;
+  out[1] = static_cast<double>(dev->status);
+}
+
 __global__ void dev_init_kernel(FilterDev* dev, double sum, float maxval) {
   FilterDev d = {};
   d.log_norm = 0.0;
@@ -293,13 +302,13 @@ hipError_t launch_init_uniform(int dtype, void* buf0, void* buf1, const uint8_t*
   return hipGetLastError();
 }
 
-hipError_t launch_slice_from_f32(int dtype, const float* src, void* dst, int W, int H, int pitch,
+hipError_t launch_slice_from_f32(int dtype, const float* src, void* dst, int W, int H, int pitch, float factor,
                                  hipStream_t s) {
   dim3 grid((pitch + 255) / 256, H);
   switch (dtype) {
-    case 0: hipLaunchKernelGGL(slice_from_f32_kernel<float>, grid, dim3(256), 0, s, src, static_cast<float*>(dst), W, H, pitch); break;
-    case 1: hipLaunchKernelGGL(slice_from_f32_kernel<__bf16>, grid, dim3(256), 0, s, src, static_cast<__bf16*>(dst), W, H, pitch); break;
-    case 2: hipLaunchKernelGGL(slice_from_f32_kernel<_Float16>, grid, dim3(256), 0, s, src, static_cast<_Float16*>(dst), W, H, pitch); break;
+    case 0: hipLaunchKernelGGL(slice_from_f32_kernel<float>, grid, dim3(256), 0, s, src, static_cast<float*>(dst), W, H, pitch, factor); break;
+    case 1: hipLaunchKernelGGL(slice_from_f32_kernel<__bf16>, grid, dim3(256), 0, s, src, static_cast<__bf16*>(dst), W, H, pitch, factor); break;
+    case 2: hipLaunchKernelGGL(slice_from_f32_kernel<_Float16>, grid, dim3(256), 0, s, src, static_cast<_Float16*>(dst), W, H, pitch, factor); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -344,6 +353,24 @@ hipError_t launch_write_shifts(const int32_t* n, int count, int32_t* dst, hipStr
   ShiftList l;
   for (int i = 0; i < 2 * count; ++i) l.n[i] = n[i];
   hipLaunchKernelGGL(write_shifts_kernel, dim3(1), dim3(256), 0, s, l, count, dst);
+  return hipGetLastError();
+}
+
+hipError_t launch_write_table(const ShiftEntry* t, int count, ShiftEntry* dst, hipStream_t s) {
+  if (count < 1 || count > kMaxTheta) return hipErrorInvalidValue;
+  for (int k0 = 0; k0 < count; k0 += kArgTableMax) {
+    const int n = count - k0 < kArgTableMax ? count - k0 : kArgTableMax;
+    ShiftArgs a;
+    for (int i = 0; i < n; ++i) a.e[i] = t[k0 + i];
+    hipLaunchKernelGGL(write_table_kernel, dim3(1), dim3(128), 0, s, a, n, dst + k0);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t launch_export_scalars(const FilterDev* dev, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(export_scalars_kernel, dim3(1), dim3(1), 0, s, dev, out);
   return hipGetLastError();
 }
 

@@ -68,6 +68,20 @@ __device__ inline bool arrive_last(FilterDev* dev, uint32_t blk, uint32_t nblock
   return __hip_atomic_fetch_add(&dev->counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == groups - 1;
 }
 
+// Warp of one heading channel: source offset (nx, ny) in whole cells and the
+// bilinear fractions (fx, fy) of the displacement R(psi_k) [u, v] / cell,
+// computed on the host in FP64 (floor and remainder) and rounded to FP32.
+struct ShiftEntry {
+  int32_t nx, ny;
+  float fx, fy;
+};
+// Heading counts up to this many pass their shift table in the kernel
+// arguments of a single-filter step (16 bytes per channel).
+constexpr int kArgTableMax = 128;
+struct ShiftArgs {
+  ShiftEntry e[kArgTableMax];
+};
+
 // Everything one step of one filter needs.  Passed by value for a single
 // filter, or from device memory for a batch.
 struct StepArgs {
@@ -85,6 +99,8 @@ struct StepArgs {
   float gxy[kMaxTaps];        // x/y taps, centred at index R of the kernel radius
   float gth[kMaxTaps];        // theta taps
   const int32_t* ishift;      // whole-cell shifts (nx, ny) per channel, or null: computed from u, v
+  const ShiftEntry* table;    // streaming kernel: per-channel shift table in device memory, or null
+                              // (then the table travels in the kernel arguments)
 };
 
 // Odometry step with anisotropic, heading-rotated noise (aniso.hip).
@@ -161,19 +177,26 @@ constexpr int kStreamAlignBytes = 32;
 // Launch shape of the step kernel.  tx > 0: tiled kernel with tx x ty tiles
 // and nt threads.  tx == 0: streaming kernel with ty-row strips, nt / 64
 // waves and nbuf source-slice buffers.
+// variant (streaming kernel only): 0 = x blur by lane shifts before the
+// theta ring, 1 = mask folded into the y taps, theta blur first and the x
+// blur through a per-wave LDS row, host shift table.
 struct KernelShape {
-  int tx = 64, ty = 16, nt = 256, nbuf = 2;
+  int tx = 64, ty = 16, nt = 256, nbuf = 2, variant = 0;
   bool operator==(const KernelShape& o) const {
-    return tx == o.tx && ty == o.ty && nt == o.nt && nbuf == o.nbuf;
+    return tx == o.tx && ty == o.ty && nt == o.nt && nbuf == o.nbuf && variant == o.variant;
   }
   bool operator<(const KernelShape& o) const {
     if (tx != o.tx) return tx < o.tx;
     if (ty != o.ty) return ty < o.ty;
     if (nt != o.nt) return nt < o.nt;
-    return nbuf < o.nbuf;
+    if (nbuf != o.nbuf) return nbuf < o.nbuf;
+    return variant < o.variant;
   }
 };
-hipError_t launch_step(int dtype, int radius, const KernelShape& k, const StepArgs& a, hipStream_t s);
+// tab: the shift table of a single-filter step when n_theta <= kArgTableMax
+// and a.table is null (variant 1); ignored otherwise.
+hipError_t launch_step(int dtype, int radius, const KernelShape& k, const StepArgs& a, const ShiftArgs* tab,
+                       hipStream_t s);
 // jobs_dev[0..njobs) with first_dev[j] = first workgroup of job j (first_dev[njobs] = total);
 // max_theta = the largest heading count among the jobs.
 hipError_t launch_step_batch(int dtype, int radius, const KernelShape& k, const StepArgs* jobs_dev,
@@ -186,16 +209,22 @@ hipError_t launch_map_setup(const uint8_t* occ_dev, int W, int H, int pitch, con
                             float* wt, hipStream_t s);
 hipError_t launch_init_uniform(int dtype, void* buf0, void* buf1, const uint8_t* free8, int W, int H,
                                int pitch, int n_theta, int64_t sstride, hipStream_t s);
+// dst_slice = src * factor, converted to the storage type (pitch layout).
 hipError_t launch_slice_from_f32(int dtype, const float* src, void* dst_slice, int W, int H,
-                                 int pitch, hipStream_t s);
+                                 int pitch, float factor, hipStream_t s);
 hipError_t launch_reduce(int dtype, const ReduceArgs& a, int nblocks, hipStream_t s);
 hipError_t launch_export(int dtype, const void* buf, int W, int H, int pitch, int n_theta,
                          int64_t sstride, const FilterDev* dev, float* out, int64_t out_slice_stride,
                          int k_begin, int k_end, float* map_out, hipStream_t s);
 hipError_t launch_dev_init(FilterDev* dev, double sum, float maxval, hipStream_t s);
+// out[0] = log-normaliser, out[1] = sticky status (device, two doubles).
+hipError_t launch_export_scalars(const FilterDev* dev, double* out, hipStream_t s);
 // Write n[0 .. 2*count) (whole-cell shifts, nx ny per channel) to device memory
 // through the kernel's arguments: no host-side synchronisation.
 hipError_t launch_write_shifts(const int32_t* n, int count, int32_t* dst, hipStream_t s);
+// Write a shift table t[0 .. count) to device memory through kernel
+// arguments (kArgTableMax entries per launch).
+hipError_t launch_write_table(const ShiftEntry* t, int count, ShiftEntry* dst, hipStream_t s);
 
 // Floyd-Steinberg sample selection (sample.hip).  src: H x W dense FP32,
 // either the intensity itself (scaled == false) or the belief map, turned into

@@ -179,7 +179,7 @@ __host__ __device__ inline int64_t tiled_offset(int64_t cell, int beta, int64_t 
 // step][lane]), so the four waves share it instead of each streaming it from
 // L2; only when all blocks fit one pass (nblocks == NCH) and KPAD > 0.
 template <typename OP, typename T, int MODE, int NCH, int KPAD, bool BL = false>
-__global__ __launch_bounds__(kScanThreads) void scan_gemm_kernel(ScanArgs a) {
+__device__ __forceinline__ void scan_gemm_body(const ScanArgs& a, const int tile, const int ntiles) {
   constexpr int kNChunk = NCH;  // 32-wide channel blocks held in accumulators at once
   static_assert(!BL || KPAD > 0, "the staged operand needs a compile-time depth");
   __shared__ float red_v[kScanThreads];
@@ -192,7 +192,7 @@ __global__ __launch_bounds__(kScanThreads) void scan_gemm_kernel(ScanArgs a) {
   const int t = threadIdx.x;
   const int lane = t & 63, wv = t >> 6;
   const int half = lane >> 5, col = lane & 31;
-  const int cell0 = blockIdx.x * kTileCells + wv * 32;
+  const int cell0 = tile * kTileCells + wv * 32;
   const OP* ct = static_cast<const OP*>(a.ct);
   FilterDev* dev = a.dev;
   const T* bel = static_cast<const T*>(a.buf[dev->cur]);
@@ -376,7 +376,7 @@ __global__ __launch_bounds__(kScanThreads) void scan_gemm_kernel(ScanArgs a) {
         if (lb > -INFINITY) {
           const int d = dist(b, g, i, srv[g][i]);
           const float L = lb - a.c * static_cast<float>(d);
-          const int idx = k * kTileCells + (cb + i - static_cast<int>(blockIdx.x) * kTileCells);
+          const int idx = k * kTileCells + (cb + i - static_cast<int>(tile) * kTileCells);
           if (L > best || (L == best && idx < best_idx)) {
             best = L;
             best_idx = idx;
@@ -410,7 +410,7 @@ __global__ __launch_bounds__(kScanThreads) void scan_gemm_kernel(ScanArgs a) {
   const float ref_lb = red_lb[0];
   if (t == 0) {
     // L_ref in FP64 from the stored value and the exact integer distance
-    publish(&a.partials[blockIdx.x], has_ref ? static_cast<double>(ref_lb) - static_cast<double>(a.c) * ref_d : -INFINITY);
+    publish(&a.partials[tile], has_ref ? static_cast<double>(ref_lb) - static_cast<double>(a.c) * ref_d : -INFINITY);
   }
   // write L - L_ref for every state of the tile (both terms are differences
   // of nearby quantities: no large cancellation)
@@ -435,12 +435,12 @@ __global__ __launch_bounds__(kScanThreads) void scan_gemm_kernel(ScanArgs a) {
   // last workgroup: M* = max over tiles
   __syncthreads();
   if (t == 0) {
-    last_flag = arrive_last(dev, blockIdx.x, gridDim.x);
+    last_flag = arrive_last(dev, tile, ntiles);
   }
   __syncthreads();
   if (!last_flag) return;
   double m = -INFINITY;
-  for (int b = t; b < static_cast<int>(gridDim.x); b += kScanThreads)
+  for (int b = t; b < ntiles; b += kScanThreads)
     m = fmax(m, __hip_atomic_load(&a.partials[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
   red_m[t] = m;
   __syncthreads();
@@ -455,12 +455,34 @@ __global__ __launch_bounds__(kScanThreads) void scan_gemm_kernel(ScanArgs a) {
   }
 }
 
+template <typename OP, typename T, int MODE, int NCH, int KPAD, bool BL = false>
+__global__ __launch_bounds__(kScanThreads) void scan_gemm_kernel(ScanArgs a) {
+  scan_gemm_body<OP, T, MODE, NCH, KPAD, BL>(a, blockIdx.x, gridDim.x);
+}
+
+// The scans of several filters of one map in one launch: every workgroup
+// takes its 128-cell tile of the table for each filter in turn, so the tile
+// is read from memory once and from the caches for the other filters.
+constexpr int kScanBatchMax = 16;
+struct ScanJobs {
+  ScanArgs a[kScanBatchMax];
+  int32_t n;
+};
+
+template <typename OP, typename T, int NCH, int KPAD, bool BL>
+__global__ __launch_bounds__(kScanThreads) void scan_gemm_batch_kernel(ScanJobs jobs) {
+  for (int j = 0; j < jobs.n; ++j) {
+    scan_gemm_body<OP, T, 0, NCH, KPAD, BL>(jobs.a[j], blockIdx.x, gridDim.x);
+    __syncthreads();  // shared arrays are reused by the next filter
+  }
+}
+
 // ---- pass 2: exponentiate, store, renormalise ------------------------------------------
 // Grid (bx, channel): block (bx, k) walks runs of four cells of plane k with
 // a stride of gridDim.x runs, so every access is a 16-byte (FP32) piece and
 // the tile of a cell is a shift, not a 64-bit division.
 template <typename T>
-__global__ __launch_bounds__(kScanThreads) void scan_apply_kernel(ScanArgs a) {
+__device__ __forceinline__ void scan_apply_body(const ScanArgs& a, const int bx, const int nbx, const int k) {
   __shared__ double rs[kScanThreads];
   __shared__ float rm[kScanThreads];
   __shared__ int last_flag;
@@ -468,15 +490,14 @@ __global__ __launch_bounds__(kScanThreads) void scan_apply_kernel(ScanArgs a) {
   FilterDev* dev = a.dev;
   const double mstar = dev->aux[0];
   if (!(mstar > -INFINITY)) return;  // degenerate: keep the belief (uniform across the grid)
-  const int k = blockIdx.y;
-  const int blk = k * gridDim.x + blockIdx.x;
-  const int nblk = gridDim.x * gridDim.y;
+  const int blk = k * nbx + bx;
+  const int nblk = nbx * a.n_theta;
   T* plane = static_cast<T*>(a.buf[dev->cur]) + static_cast<int64_t>(k) * a.sstride;
   const float* lplane = a.lrel + static_cast<int64_t>(k) * a.sstride;
   double* part = a.partials + a.tiles;
   const int nquads = static_cast<int>(a.sstride / 4);
   float s = 0.f, mx = 0.f;
-  for (int q = blockIdx.x * kScanThreads + t; q < nquads; q += gridDim.x * kScanThreads) {
+  for (int q = bx * kScanThreads + t; q < nquads; q += nbx * kScanThreads) {
     const int cell = 4 * q;
     const double mt = a.partials[cell / kTileCells];
     const float4 lr = *reinterpret_cast<const float4*>(lplane + cell);
@@ -539,6 +560,19 @@ __global__ __launch_bounds__(kScanThreads) void scan_apply_kernel(ScanArgs a) {
     }
     __hip_atomic_store(&dev->counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kScanThreads) void scan_apply_kernel(ScanArgs a) {
+  scan_apply_body<T>(a, blockIdx.x, gridDim.x, blockIdx.y);
+}
+
+// pass 2 of several filters: blockIdx.z is the filter, blockIdx.y the channel
+template <typename T>
+__global__ __launch_bounds__(kScanThreads) void scan_apply_batch_kernel(ScanJobs jobs) {
+  const ScanArgs& a = jobs.a[blockIdx.z];
+  if (static_cast<int>(blockIdx.y) >= a.n_theta) return;
+  scan_apply_body<T>(a, blockIdx.x, gridDim.x, blockIdx.y);
 }
 
 // ---- sampled observation update ---------------------------------------------------------
@@ -1210,6 +1244,38 @@ hipError_t build_ct(const ScanLaunch& L, const float* ranges_m, CtArgs& ca, int6
 
 }  // namespace
 
+namespace {
+
+// Arguments of both passes for one filter, after its circulant operand.
+ScanArgs scan_args_for(const ScanLaunch& L, const CtArgs& ca, int64_t sz, double sigma_m, int32_t* dout) {
+  const ScanTable& t = *L.table;
+  const double h = t.max_range / 256.0;
+  ScanArgs a = {};
+  a.rq = t.rq;
+  a.sr = t.sr;
+  a.ct = L.work.c;
+  a.buf[0] = L.buf[0];
+  a.buf[1] = L.buf[1];
+  a.lrel = L.scratch;
+  a.dout = dout;
+  a.partials = L.partials;
+  a.dev = L.dev;
+  a.cells = L.H * L.pitch;
+  a.n_theta = L.n_theta;
+  a.npad = ca.npad;
+  a.kpad = t.kpad;
+  a.W = L.W;
+  a.pitch = L.pitch;
+  a.sstride = L.sstride;
+  a.sz = static_cast<int32_t>(sz);
+  a.c = static_cast<float>(h * h / (2.0 * sigma_m * sigma_m));
+  a.tiles = (a.cells + kTileCells - 1) / kTileCells;
+  a.rq_bytes = static_cast<uint32_t>(t.rq_bytes);
+  return a;
+}
+
+}  // namespace
+
 hipError_t scan_launch(const ScanLaunch& L, const float* ranges_m, double sigma_m, int32_t* dout) {
   const ScanTable& t = *L.table;
   const double h = t.max_range / 256.0;
@@ -1301,6 +1367,97 @@ hipError_t scan_launch(const ScanLaunch& L, const float* ranges_m, double sigma_
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+hipError_t scan_launch_batch(const ScanLaunch* Ls, int n, const float* ranges_m, const double* sigma_m) {
+  if (n < 1) return hipSuccess;
+  const ScanTable& t = *Ls[0].table;
+  const hipStream_t stream = Ls[0].stream;
+  // circulant operands, then the filters grouped by storage type and heading
+  // count (the kernels' template arguments and the pass-2 grid, which sets the
+  // reduction order: each filter reduces as it would alone), kScanBatchMax per
+  // launch
+  std::vector<std::pair<int64_t, int>> order;  // (group key, filter)
+  std::vector<ScanArgs> args(n);
+  for (int i = 0; i < n; ++i) {
+    CtArgs ca;
+    int64_t sz = 0;
+    const hipError_t e = build_ct(Ls[i], ranges_m + static_cast<int64_t>(i) * t.n_dirs, ca, &sz);
+    if (e != hipSuccess) return e;
+    args[i] = scan_args_for(Ls[i], ca, sz, sigma_m[i], nullptr);
+    order.push_back({static_cast<int64_t>(Ls[i].dtype) * 4096 + Ls[i].n_theta, i});
+  }
+  std::stable_sort(order.begin(), order.end(),
+                   [](const std::pair<int64_t, int>& x, const std::pair<int64_t, int>& y) { return x.first < y.first; });
+  for (size_t g0 = 0; g0 < order.size();) {
+    size_t g1 = g0;
+    while (g1 < order.size() && order[g1].first == order[g0].first && g1 - g0 < kScanBatchMax) ++g1;
+    ScanJobs jobs = {};
+    jobs.n = static_cast<int32_t>(g1 - g0);
+    int max_theta = 0;
+    for (size_t q = g0; q < g1; ++q) {
+      jobs.a[q - g0] = args[order[q].second];
+      max_theta = std::max(max_theta, jobs.a[q - g0].n_theta);
+    }
+    const int dtype = Ls[order[g0].second].dtype;
+    const ScanArgs& a0 = jobs.a[0];
+    const dim3 g1d(a0.tiles), b1(kScanThreads);
+    const int nch = std::min(kMaxNChunk, a0.npad / 32);
+    const bool stage_b = !t.f32 && t.kpad == 384 && a0.npad / 32 <= 3;
+    if (stage_b) {
+      switch (dtype * 8 + nch) {
+#define MCL_GEMMB_BL(DT, T_)                                                                                               \
+  case DT * 8 + 1: hipLaunchKernelGGL((scan_gemm_batch_kernel<__bf16, T_, 1, 384, true>), g1d, b1, 0, stream, jobs); break; \
+  case DT * 8 + 2: hipLaunchKernelGGL((scan_gemm_batch_kernel<__bf16, T_, 2, 384, true>), g1d, b1, 0, stream, jobs); break; \
+  case DT * 8 + 3: hipLaunchKernelGGL((scan_gemm_batch_kernel<__bf16, T_, 3, 384, true>), g1d, b1, 0, stream, jobs); break;
+        MCL_GEMMB_BL(0, float)
+        MCL_GEMMB_BL(1, __bf16)
+        MCL_GEMMB_BL(2, _Float16)
+#undef MCL_GEMMB_BL
+        default: return hipErrorInvalidValue;
+      }
+    } else {
+#define MCL_GEMMB_K(OP, T_, KP)                                                                                          \
+  switch (nch) {                                                                                                        \
+    case 1: hipLaunchKernelGGL((scan_gemm_batch_kernel<OP, T_, 1, KP, false>), g1d, b1, 0, stream, jobs); break;        \
+    case 2: hipLaunchKernelGGL((scan_gemm_batch_kernel<OP, T_, 2, KP, false>), g1d, b1, 0, stream, jobs); break;        \
+    case 3: hipLaunchKernelGGL((scan_gemm_batch_kernel<OP, T_, 3, KP, false>), g1d, b1, 0, stream, jobs); break;        \
+    default: hipLaunchKernelGGL((scan_gemm_batch_kernel<OP, T_, 4, KP, false>), g1d, b1, 0, stream, jobs); break;       \
+  }
+#define MCL_GEMMB(OP, T_)          \
+  do {                              \
+    if (t.kpad == 384) {            \
+      MCL_GEMMB_K(OP, T_, 384)      \
+    } else {                        \
+      MCL_GEMMB_K(OP, T_, 0)        \
+    }                               \
+  } while (0)
+      switch (dtype * 2 + (t.f32 ? 1 : 0)) {
+        case 0: MCL_GEMMB(__bf16, float); break;
+        case 1: MCL_GEMMB(float, float); break;
+        case 2: MCL_GEMMB(__bf16, __bf16); break;
+        case 3: MCL_GEMMB(float, __bf16); break;
+        case 4: MCL_GEMMB(__bf16, _Float16); break;
+        case 5: MCL_GEMMB(float, _Float16); break;
+        default: return hipErrorInvalidValue;
+      }
+#undef MCL_GEMMB
+#undef MCL_GEMMB_K
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    // pass 2: the per-filter grid of scan_launch, the filter in z
+    const dim3 g2(std::max(1, std::min(64, kScanApplyBlocks / max_theta)), max_theta, jobs.n);
+    switch (dtype) {
+      case 0: hipLaunchKernelGGL(scan_apply_batch_kernel<float>, g2, dim3(kScanThreads), 0, stream, jobs); break;
+      case 1: hipLaunchKernelGGL(scan_apply_batch_kernel<__bf16>, g2, dim3(kScanThreads), 0, stream, jobs); break;
+      case 2: hipLaunchKernelGGL(scan_apply_batch_kernel<_Float16>, g2, dim3(kScanThreads), 0, stream, jobs); break;
+      default: return hipErrorInvalidValue;
+    }
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    g0 = g1;
+  }
+  return hipSuccess;
 }
 
 hipError_t scan_sampled_launch(const ScanLaunch& L, const float* ranges_m, double sigma_m, const uint8_t* mask,

@@ -49,6 +49,10 @@ struct ScanLaunch {
 
 // Enqueue the scan update (dout == nullptr) or the diagnostic distance output.
 hipError_t scan_launch(const ScanLaunch& L, const float* ranges_m, double sigma_m, int32_t* dout);
+// Enqueue the scan updates of n filters of one map on Ls[0].stream: ranges_m
+// holds n scans of the table's n_dirs beams, sigma_m one std-dev per filter.
+// Each filter's result is bitwise that of scan_launch.
+hipError_t scan_launch_batch(const ScanLaunch* Ls, int n, const float* ranges_m, const double* sigma_m);
 // Enqueue the sampled update on the cells of `mask` (H x W dense, nonzero =
 // selected).  list and pos: H * pitch int32 each (sample list and positions).
 hipError_t scan_sampled_launch(const ScanLaunch& L, const float* ranges_m, double sigma_m, const uint8_t* mask,

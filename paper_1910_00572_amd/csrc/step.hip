@@ -829,6 +829,607 @@ __device__ __forceinline__ void stream_body(const StepArgs& a, const int blk, co
   finalize_step<NT>(a, dev, nblk, scale, cur, red_s, red_m);
 }
 
+// ---- streaming variant with the mask in the y taps and the x blur last --------------
+// Same strips, waves and theta ring as stream_body, with three changes that
+// take VALU work off every channel:
+//  * the pre-blur mask is folded into the y taps: each lane holds, per output
+//    row o, the taps g_y[l] M(y0 - R + o + l), so the masked S rows are never
+//    formed (M is 0 or 1, so the products are exact);
+//  * the ring holds y-blurred rows; the emit blurs over theta first and then
+//    along x (the two blurs commute: no mask sits between them), reading the
+//    neighbouring lanes' theta-blurred values from a per-wave LDS row instead
+//    of chaining lane shifts;
+// The shift table (whole-cell offsets and bilinear fractions per channel) is
+// computed on the host and read with scalar loads; row offsets go in the
+// buffer instructions' scalar offset, which the range check includes.
+template <typename T>
+__device__ inline float load_row(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff);
+template <>
+__device__ inline float load_row<float>(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+template <>
+__device__ inline float load_row<__bf16>(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+  return __uint_as_float(static_cast<uint32_t>(__builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0)) << 16);
+}
+template <>
+__device__ inline float load_row<_Float16>(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+  return static_cast<float>(__builtin_bit_cast(_Float16, __builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0)));
+}
+template <typename T>
+__device__ inline void store_row(float v, __amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff);
+template <>
+__device__ inline void store_row<float>(float v, __amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, voff, soff, 0);
+}
+template <>
+__device__ inline void store_row<__bf16>(float v, __amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+  __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, static_cast<__bf16>(v)), r, voff, soff, 0);
+}
+template <>
+__device__ inline void store_row<_Float16>(float v, __amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+  __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, static_cast<_Float16>(v)), r, voff, soff, 0);
+}
+
+// The shift table as constant memory: loads at a uniform index become scalar
+// loads (the table is not written while a step runs).
+typedef const __attribute__((address_space(4))) ShiftEntry* ConstTable;
+__device__ inline ConstTable const_table(const ShiftEntry* p) { return (ConstTable)p; }
+
+template <typename T, int R, int TY, int WAVES, int NBUF>
+__device__ __forceinline__ void stream2_body(const StepArgs& a, const ShiftEntry* __restrict__ tab, const int blk,
+                                             const int nblk) {
+  constexpr int NT = 64 * WAVES;
+  constexpr int NS = TY + 2 * R;   // S rows
+  constexpr int NR = NS + 1;       // source rows
+  constexpr int GW = WAVES;        // channels per group (one per wave)
+  // ring slots: between two barriers a wave emits one group (2R + GW
+  // channels) while the group after it is written
+  constexpr int RS = 2 * R + 2 * GW;
+  constexpr int TAPS = 2 * R + 1;
+  constexpr int LP = (TY / 4) % 2 == 1 ? TY : TY + 4;      // odd number of 16-byte units per lane
+  constexpr int ZL = 64 + 2 * R;                           // x-blur row: R zero lanes on each side
+  constexpr int EB = Elt<T>::BYTES;
+  static_assert(TY % 4 == 0, "rows per strip must be a multiple of 4");
+  static_assert(NBUF == 1 || NBUF == 2, "one or two source-slice buffers");
+  static_assert(sizeof(float) * RS * 64 * LP >= NT * (sizeof(double) + sizeof(float)), "reduction fits the ring");
+
+  __shared__ __attribute__((aligned(16))) float ring[RS][64][LP];
+  __shared__ __attribute__((aligned(16))) float zrow[WAVES][ZL][LP];
+  __shared__ int last_flag;
+  double* red_s = reinterpret_cast<double*>(&ring[0][0][0]);
+  float* red_m = reinterpret_cast<float*>(red_s + NT);
+
+  const int t = threadIdx.x;
+  const int lane = t & 63;
+  const int w = __builtin_amdgcn_readfirstlane(t >> 6);
+  const int H = a.H, pitch = a.pitch, nth = a.n_theta;
+  const int64_t sstride = a.sstride;
+  const uint32_t row_bytes = static_cast<uint32_t>(pitch) * EB;
+  const uint32_t plane_bytes = static_cast<uint32_t>(sstride) * EB;  // < 2^30 (host-checked)
+  const int tiles_x = a.tiles_x;
+  const int ntile = tiles_x * a.tiles_y;
+  const int chunk = blk / ntile, tile = blk % ntile;
+  const int strip = a.strip;
+  const int xb = (tile % tiles_x) * strip - (R + 1);
+  const int y0 = (tile / tiles_x) * TY;
+  const int x = xb + lane;
+  const int kbeg = chunk * a.chunk_len;
+  const int kend = min(nth, kbeg + a.chunk_len);
+  const int nk = kend - kbeg;
+  const int count = nk + 2 * R;  // relative channels warped: the chunk and R on each side
+  const int jbeg = kbeg - R;
+  FilterDev* dev = a.dev;
+  const int cur = dev->cur;
+  const float scale = dev->scale;
+  const T* __restrict__ bin = static_cast<const T*>(a.buf[cur]);
+  T* __restrict__ bout = static_cast<T*>(a.buf[cur ^ 1]);
+
+  // zero lanes on both sides of every wave's x-blur row
+  for (int i = t; i < WAVES * 2 * R * LP; i += NT) {
+    const int wv = i / (2 * R * LP), rem = i % (2 * R * LP);
+    const int ln = rem / LP, e = rem % LP;
+    zrow[wv][ln < R ? ln : 64 + ln][e] = 0.f;
+  }
+  float gt[TAPS], gx[TAPS];
+#pragma unroll
+  for (int l = 0; l < TAPS; ++l) {
+    gt[l] = a.gth[l];
+    gx[l] = a.gxy[l];
+  }
+  const bool xin = x >= 0 && x < pitch;
+  // masked y taps: gm[o][l] = g_y[l] M(row y0 - R + o + l)
+  float gm[TY][TAPS];
+  {
+    float mreg[NS];
+#pragma unroll
+    for (int r = 0; r < NS; ++r) {
+      const int y = y0 - R + r;
+      mreg[r] = (xin && y >= 0 && y < H) ? a.mpre[static_cast<int64_t>(y) * pitch + x] : 0.f;
+    }
+#pragma unroll
+    for (int o = 0; o < TY; ++o)
+#pragma unroll
+      for (int l = 0; l < TAPS; ++l) gm[o][l] = gx[l] * mreg[o + l];
+  }
+  const bool out_lane = lane >= R + 1 && lane <= R + strip && xin;
+  float wreg[TY];
+#pragma unroll
+  for (int o = 0; o < TY; ++o) {
+    const int y = y0 + o;
+    wreg[o] = (out_lane && y < H) ? a.wt[static_cast<int64_t>(y) * pitch + x] * scale : 0.f;
+  }
+  const uint32_t soff = out_lane ? static_cast<uint32_t>(x) * EB : kColOut;
+  auto phys = [nth](int j) {
+    int k = j % nth;
+    return k < 0 ? k + nth : k;
+  };
+  __syncthreads();  // zero lanes written
+
+  struct Slice {
+    float v[NR];
+    float fx, fy;
+  };
+  // Source rows of relative channel c, one group ahead (no branch around the
+  // loads: channels past the end read through an empty descriptor).
+  auto load_slice = [&](int c, Slice& sl) {
+    const bool live = c < count;
+    const int kp = phys(jbeg + (live ? c : 0));
+    // uniform index into a table that no workgroup writes: scalar loads
+    const ConstTable e = const_table(tab) + kp;
+    const int nx = __builtin_amdgcn_readfirstlane(e->nx);
+    const int ny = __builtin_amdgcn_readfirstlane(e->ny);
+    sl.fx = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, e->fx)));
+    sl.fy = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, e->fy)));
+    const int cx = x - nx;
+    const uint32_t loff = static_cast<unsigned>(cx) < static_cast<unsigned>(pitch) ? static_cast<uint32_t>(cx) * EB
+                                                                                    : kColOut;
+    const int sy0 = y0 - R - ny - 1;
+    const __amdgpu_buffer_rsrc_t rs = buf_rsrc(bin + static_cast<int64_t>(kp) * sstride, live ? plane_bytes : 0u);
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      const int sy = sy0 + r;
+      const uint32_t roff = static_cast<unsigned>(sy) < static_cast<unsigned>(H) ? static_cast<uint32_t>(sy) * row_bytes
+                                                                                 : kRowOut;
+      sl.v[r] = load_row<T>(rs, loff, roff);
+    }
+  };
+  // bilinear warp and masked y blur of relative channel c into its ring slot
+  auto process = [&](int c, Slice& sl) {
+    float(&vv)[NR] = sl.v;
+    const float fx = sl.fx, fy = sl.fy;
+#pragma unroll
+    for (int r = 0; r < NR; ++r) vv[r] = fmaf(fx, from_left(vv[r]) - vv[r], vv[r]);
+#pragma unroll
+    for (int r = 0; r < NS; ++r) vv[r] = fmaf(fy, vv[r] - vv[r + 1], vv[r + 1]);
+    float* slot = &ring[c % RS][lane][0];
+#pragma unroll
+    for (int o4 = 0; o4 < TY; o4 += 4) {
+      float p4[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int o = o4 + q;
+        float yv = gm[o][0] * vv[o];
+#pragma unroll
+        for (int l = 1; l < TAPS; ++l) yv = fmaf(gm[o][l], vv[o + l], yv);
+        p4[q] = yv;
+      }
+      *reinterpret_cast<float4*>(slot + o4) = make_float4(p4[0], p4[1], p4[2], p4[3]);
+    }
+  };
+  float psum = 0.f, pmax = 0.f;
+  float* zmine = &zrow[w][lane + R][0];
+  // Output channel of group g for this wave, in two parts so that the ring
+  // reads are in flight while the next group is warped: emit_read issues the
+  // theta ring reads; emit_finish blurs over theta into the wave's x-blur row,
+  // blurs along x from the neighbouring lanes, applies the post-blur weights,
+  // stores and reduces.
+  typedef float4 RingRead[TY / 4][TAPS];
+  auto emit_read = [&](int g, RingRead& rv) {
+    const int krel = GW * g - 2 * R + w;
+    // ring slots of channels krel .. krel + 2R; krel >= -(2R + GW) (padding
+    // emits), so a multiple of RS keeps the modulus non-negative
+    constexpr int OFF = ((2 * R + GW + RS - 1) / RS) * RS;
+    int slot = (krel + OFF) % RS;
+#pragma unroll
+    for (int l = 0; l < TAPS; ++l) {
+#pragma unroll
+      for (int b = 0; b < TY / 4; ++b) rv[b][l] = *reinterpret_cast<const float4*>(&ring[slot][lane][4 * b]);
+      slot = slot + 1 == RS ? 0 : slot + 1;
+    }
+  };
+  auto emit_finish = [&](int g, RingRead& rv) {
+    const int krel = GW * g - 2 * R + w;
+    const bool live = krel >= 0 && krel < nk;
+    const int ko = kbeg + (live ? krel : 0);
+    const __amdgpu_buffer_rsrc_t rs = buf_rsrc(bout + static_cast<int64_t>(ko) * sstride, live ? plane_bytes : 0u);
+#pragma unroll
+    for (int b = 0; b < TY / 4; ++b) {
+      float z[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int l = 0; l < TAPS; ++l) {
+        z[0] = fmaf(gt[l], rv[b][l].x, z[0]);
+        z[1] = fmaf(gt[l], rv[b][l].y, z[1]);
+        z[2] = fmaf(gt[l], rv[b][l].z, z[2]);
+        z[3] = fmaf(gt[l], rv[b][l].w, z[3]);
+      }
+      *reinterpret_cast<float4*>(zmine + 4 * b) = make_float4(z[0], z[1], z[2], z[3]);
+    }
+    // the x-blur row is written and read by this wave only: LDS operations
+    // of one wave complete in order, so a wave-scope fence suffices
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    float es = 0.f, em = 0.f;
+#pragma unroll
+    for (int ob = 0; ob < TY; ob += 4) {
+      float4 zv[TAPS];
+#pragma unroll
+      for (int l = 0; l < TAPS; ++l) zv[l] = *reinterpret_cast<const float4*>(zmine + (l - R) * LP + ob);
+      float o4[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int l = 0; l < TAPS; ++l) {
+        o4[0] = fmaf(gx[l], zv[l].x, o4[0]);
+        o4[1] = fmaf(gx[l], zv[l].y, o4[1]);
+        o4[2] = fmaf(gx[l], zv[l].z, o4[2]);
+        o4[3] = fmaf(gx[l], zv[l].w, o4[3]);
+      }
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int o = ob + e;
+        const float ov = o4[e] * wreg[o];
+        es += ov;
+        em = fmaxf(em, ov);
+        const int y = y0 + o;
+        const uint32_t roff = y < H ? static_cast<uint32_t>(y) * row_bytes : kRowOut;
+        store_row<T>(ov, rs, soff, roff);
+      }
+    }
+    if (live) {
+      psum += es;
+      pmax = fmaxf(pmax, em);
+    }
+  };
+
+  auto ch = [&](int g) { return GW * g + w; };
+  // Software pipeline: between two barriers a wave emits group g - 1 and
+  // warps group g (their ring slots are distinct), so the emit's LDS reads
+  // are in flight during the warp.  Channels past the end (the last groups)
+  // load through empty descriptors and their emits store nothing.
+  if constexpr (NBUF == 2) {
+    const int G = (((count + GW - 1) / GW) + 1) & ~1;  // even: the last may be padding
+    Slice sA, sB;
+    RingRead rv;
+    load_slice(ch(0), sA);
+    load_slice(ch(1), sB);
+    process(ch(0), sA);
+    __syncthreads();
+    for (int g = 1; g <= G; g += 2) {
+      load_slice(ch(g + 1), sA);
+      emit_read(g - 1, rv);
+      process(ch(g), sB);
+      emit_finish(g - 1, rv);
+      __syncthreads();
+      load_slice(ch(g + 2), sB);
+      emit_read(g, rv);
+      process(ch(g + 1), sA);
+      emit_finish(g, rv);
+      __syncthreads();
+    }
+  } else {
+    const int G = (count + GW - 1) / GW;
+    Slice sA;
+    RingRead rv;
+    load_slice(ch(0), sA);
+    process(ch(0), sA);
+    load_slice(ch(1), sA);
+    __syncthreads();
+    for (int g = 1; g <= G; ++g) {
+      emit_read(g - 1, rv);
+      process(ch(g), sA);
+      load_slice(ch(g + 1), sA);
+      emit_finish(g - 1, rv);
+      __syncthreads();
+    }
+  }
+  __syncthreads();  // the ring becomes the reduction buffer
+
+  red_s[t] = static_cast<double>(psum);
+  red_m[t] = pmax;
+  __syncthreads();
+#pragma unroll
+  for (int s = NT / 2; s > 0; s >>= 1) {
+    if (t < s) {
+      red_s[t] += red_s[t + s];
+      red_m[t] = fmaxf(red_m[t], red_m[t + s]);
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    publish(&a.partials[2 * blk], red_s[0]);
+    publish(&a.partials[2 * blk + 1], static_cast<double>(red_m[0]));
+    last_flag = arrive_last(dev, static_cast<uint32_t>(blk), static_cast<uint32_t>(nblk));
+  }
+  __syncthreads();
+  if (!last_flag) return;
+  finalize_step<NT>(a, dev, nblk, scale, cur, red_s, red_m);
+}
+
+// ---- streaming variant with the emit split by rows ----------------------------------
+// As stream2_body (mask in the y taps, theta blur before the x blur, host
+// shift table), but after each group's barrier wave w emits output row(s)
+// w RW .. (w + 1) RW - 1 of all GW channels of the group instead of every row
+// of one channel.  The theta blur of GW channels reads the 2R + GW ring slots
+// once per row (ring layout [slot][row][lane]), so the ring is read
+// (2R + GW) / (GW (2R + 1)) as often as with one channel per wave.  The post-
+// blur weights are folded into the x taps of the wave's rows.
+template <typename T, int R, int TY, int WAVES, int NBUF>
+__device__ __forceinline__ void stream3_body(const StepArgs& a, const ShiftEntry* __restrict__ tab, const int blk,
+                                             const int nblk) {
+  constexpr int NT = 64 * WAVES;
+  constexpr int NS = TY + 2 * R;   // S rows
+  constexpr int NR = NS + 1;       // source rows
+  constexpr int GW = WAVES;        // channels per group (one per wave)
+  constexpr int RW = TY / GW;      // output rows each wave emits
+  constexpr bool ONE_BARRIER = WAVES <= 4;
+  constexpr int RS = 2 * R + (ONE_BARRIER ? 2 : 1) * GW;  // ring slots (as stream_body)
+  constexpr int TAPS = 2 * R + 1;
+  constexpr int NSL = GW + 2 * R;                         // ring slots one emit reads
+  constexpr int ZV = GW * RW;                             // theta-blurred values per lane and emit
+  constexpr int ZP = (ZV / 4) % 2 == 1 ? ZV : ZV + 4;     // odd number of 16-byte units per lane
+  constexpr int ZL = 64 + 2 * R;                          // x-blur row: R zero lanes on each side
+  constexpr int EB = Elt<T>::BYTES;
+  static_assert(TY % GW == 0 && RW >= 1, "rows per strip must be a multiple of the waves");
+  static_assert(ZV % 4 == 0, "four theta-blurred values per 16-byte word");
+  static_assert(NBUF == 1 || NBUF == 2, "one or two source-slice buffers");
+  static_assert(sizeof(float) * RS * TY * 64 >= NT * (sizeof(double) + sizeof(float)), "reduction fits the ring");
+
+  __shared__ __attribute__((aligned(16))) float ring[RS][TY][64];
+  __shared__ __attribute__((aligned(16))) float zrow[WAVES][ZL][ZP];
+  __shared__ int last_flag;
+  double* red_s = reinterpret_cast<double*>(&ring[0][0][0]);
+  float* red_m = reinterpret_cast<float*>(red_s + NT);
+
+  const int t = threadIdx.x;
+  const int lane = t & 63;
+  const int w = __builtin_amdgcn_readfirstlane(t >> 6);
+  const int H = a.H, pitch = a.pitch, nth = a.n_theta;
+  const int64_t sstride = a.sstride;
+  const uint32_t row_bytes = static_cast<uint32_t>(pitch) * EB;
+  const uint32_t plane_bytes = static_cast<uint32_t>(sstride) * EB;  // < 2^30 (host-checked)
+  const int tiles_x = a.tiles_x;
+  const int ntile = tiles_x * a.tiles_y;
+  const int chunk = blk / ntile, tile = blk % ntile;
+  const int strip = a.strip;
+  const int xb = (tile % tiles_x) * strip - (R + 1);
+  const int y0 = (tile / tiles_x) * TY;
+  const int x = xb + lane;
+  const int kbeg = chunk * a.chunk_len;
+  const int kend = min(nth, kbeg + a.chunk_len);
+  const int nk = kend - kbeg;
+  const int count = nk + 2 * R;  // relative channels warped: the chunk and R on each side
+  const int jbeg = kbeg - R;
+  FilterDev* dev = a.dev;
+  const int cur = dev->cur;
+  const float scale = dev->scale;
+  const T* __restrict__ bin = static_cast<const T*>(a.buf[cur]);
+  T* __restrict__ bout = static_cast<T*>(a.buf[cur ^ 1]);
+
+  // zero lanes on both sides of every wave's x-blur row
+  for (int i = t; i < WAVES * 2 * R * ZP; i += NT) {
+    const int wv = i / (2 * R * ZP), rem = i % (2 * R * ZP);
+    const int ln = rem / ZP, e = rem % ZP;
+    zrow[wv][ln < R ? ln : 64 + ln][e] = 0.f;
+  }
+  float gt[TAPS], gx[TAPS];
+#pragma unroll
+  for (int l = 0; l < TAPS; ++l) {
+    gt[l] = a.gth[l];
+    gx[l] = a.gxy[l];
+  }
+  const bool xin = x >= 0 && x < pitch;
+  // masked y taps: gm[o][l] = g_y[l] M(row y0 - R + o + l)
+  float gm[TY][TAPS];
+  {
+    float mreg[NS];
+#pragma unroll
+    for (int r = 0; r < NS; ++r) {
+      const int y = y0 - R + r;
+      mreg[r] = (xin && y >= 0 && y < H) ? a.mpre[static_cast<int64_t>(y) * pitch + x] : 0.f;
+    }
+#pragma unroll
+    for (int o = 0; o < TY; ++o)
+#pragma unroll
+      for (int l = 0; l < TAPS; ++l) gm[o][l] = gx[l] * mreg[o + l];
+  }
+  // x taps weighted by the post-blur weights of this wave's output rows
+  const bool out_lane = lane >= R + 1 && lane <= R + strip && xin;
+  float wx[RW][TAPS];
+#pragma unroll
+  for (int rr = 0; rr < RW; ++rr) {
+    const int y = y0 + w * RW + rr;
+    const float wv = (out_lane && y < H) ? a.wt[static_cast<int64_t>(y) * pitch + x] * scale : 0.f;
+#pragma unroll
+    for (int l = 0; l < TAPS; ++l) wx[rr][l] = gx[l] * wv;
+  }
+  const uint32_t soff = out_lane ? static_cast<uint32_t>(x) * EB : kColOut;
+  auto phys = [nth](int j) {
+    int k = j % nth;
+    return k < 0 ? k + nth : k;
+  };
+  __syncthreads();  // zero lanes written
+
+  struct Slice {
+    float v[NR];
+    float fx, fy;
+  };
+  // Source rows of relative channel c, one group ahead (no branch around the
+  // loads: channels past the end read through an empty descriptor).
+  auto load_slice = [&](int c, Slice& sl) {
+    const bool live = c < count;
+    const int kp = phys(jbeg + (live ? c : 0));
+    // uniform index into a table that no workgroup writes: scalar loads
+    const ConstTable e = const_table(tab) + kp;
+    const int nx = __builtin_amdgcn_readfirstlane(e->nx);
+    const int ny = __builtin_amdgcn_readfirstlane(e->ny);
+    sl.fx = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, e->fx)));
+    sl.fy = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, e->fy)));
+    const int cx = x - nx;
+    const uint32_t loff = static_cast<unsigned>(cx) < static_cast<unsigned>(pitch) ? static_cast<uint32_t>(cx) * EB
+                                                                                    : kColOut;
+    const int sy0 = y0 - R - ny - 1;
+    const __amdgpu_buffer_rsrc_t rs = buf_rsrc(bin + static_cast<int64_t>(kp) * sstride, live ? plane_bytes : 0u);
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      const int sy = sy0 + r;
+      const uint32_t roff = static_cast<unsigned>(sy) < static_cast<unsigned>(H) ? static_cast<uint32_t>(sy) * row_bytes
+                                                                                 : kRowOut;
+      sl.v[r] = load_row<T>(rs, loff, roff);
+    }
+  };
+  // bilinear warp (y, then x) and masked y blur of relative channel c into its ring slot
+  auto process = [&](int c, Slice& sl) {
+    float(&vv)[NR] = sl.v;
+    const float fx = sl.fx, fy = sl.fy;
+#pragma unroll
+    for (int r = 0; r < NS; ++r) vv[r] = fmaf(fy, vv[r] - vv[r + 1], vv[r + 1]);
+#pragma unroll
+    for (int r = 0; r < NS; ++r) vv[r] = fmaf(fx, from_left(vv[r]) - vv[r], vv[r]);
+    const int sl_ = c % RS;
+#pragma unroll
+    for (int o = 0; o < TY; ++o) {
+      float yv = gm[o][0] * vv[o];
+#pragma unroll
+      for (int l = 1; l < TAPS; ++l) yv = fmaf(gm[o][l], vv[o + l], yv);
+      ring[sl_][o][lane] = yv;
+    }
+  };
+  float psum = 0.f, pmax = 0.f;
+  float* zmine = &zrow[w][lane + R][0];
+  // Group g's output channels GW g - 2R .. GW g - 2R + GW - 1, rows of this
+  // wave: theta blur from the ring into the wave's x-blur row, x blur (with
+  // the post-blur weights) from the neighbouring lanes, store, reduce.
+  auto emit = [&](int g) {
+    const int k0 = GW * g - 2 * R;
+    // ring slots of channels k0 .. k0 + GW - 1 + 2R; k0 >= -(2R + GW)
+    // (padding emits), so a multiple of RS keeps the modulus non-negative
+    constexpr int OFF = ((2 * R + GW + RS - 1) / RS) * RS;
+    int slot[NSL];
+    slot[0] = (k0 + OFF) % RS;
+#pragma unroll
+    for (int i = 1; i < NSL; ++i) slot[i] = slot[i - 1] + 1 == RS ? 0 : slot[i - 1] + 1;
+    float z[ZV];
+#pragma unroll
+    for (int rr = 0; rr < RW; ++rr) {
+      const int o = w * RW + rr;
+      float rv[NSL];
+#pragma unroll
+      for (int i = 0; i < NSL; ++i) rv[i] = ring[slot[i]][o][lane];
+#pragma unroll
+      for (int q = 0; q < GW; ++q) {
+        float acc = gt[0] * rv[q];
+#pragma unroll
+        for (int l = 1; l < TAPS; ++l) acc = fmaf(gt[l], rv[q + l], acc);
+        z[q * RW + rr] = acc;
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < ZV; i += 4) *reinterpret_cast<float4*>(zmine + i) = make_float4(z[i], z[i + 1], z[i + 2], z[i + 3]);
+    // the x-blur row is written and read by this wave only: LDS operations
+    // of one wave complete in order, so a wave-scope fence suffices
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    float acc[ZV];
+#pragma unroll
+    for (int i = 0; i < ZV; ++i) acc[i] = wx[i % RW][R] * z[i];
+#pragma unroll
+    for (int l = 0; l < TAPS; ++l) {
+      if (l == R) continue;
+#pragma unroll
+      for (int i = 0; i < ZV; i += 4) {
+        const float4 nv = *reinterpret_cast<const float4*>(zmine + (l - R) * ZP + i);
+        acc[i] = fmaf(wx[i % RW][l], nv.x, acc[i]);
+        acc[i + 1] = fmaf(wx[(i + 1) % RW][l], nv.y, acc[i + 1]);
+        acc[i + 2] = fmaf(wx[(i + 2) % RW][l], nv.z, acc[i + 2]);
+        acc[i + 3] = fmaf(wx[(i + 3) % RW][l], nv.w, acc[i + 3]);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < GW; ++q) {
+      const int kr = k0 + q;
+      const bool live = kr >= 0 && kr < nk;
+      const int ko = kbeg + (live ? kr : 0);
+      const __amdgpu_buffer_rsrc_t rs = buf_rsrc(bout + static_cast<int64_t>(ko) * sstride, live ? plane_bytes : 0u);
+      float es = 0.f, em = 0.f;
+#pragma unroll
+      for (int rr = 0; rr < RW; ++rr) {
+        const float ov = acc[q * RW + rr];
+        es += ov;
+        em = fmaxf(em, ov);
+        const int y = y0 + w * RW + rr;
+        const uint32_t roff = y < H ? static_cast<uint32_t>(y) * row_bytes : kRowOut;
+        store_row<T>(ov, rs, soff, roff);
+      }
+      if (live) {
+        psum += es;
+        pmax = fmaxf(pmax, em);
+      }
+    }
+  };
+
+  auto ch = [&](int g) { return GW * g + w; };
+  if constexpr (NBUF == 2) {
+    const int G = (((count + GW - 1) / GW) + 1) & ~1;
+    Slice sA, sB;
+    load_slice(ch(0), sA);
+    emit(-1);
+    for (int g = 0; g < G; g += 2) {
+      load_slice(ch(g + 1), sB);
+      process(ch(g), sA);
+      __syncthreads();
+      emit(g);
+      if (!ONE_BARRIER) __syncthreads();
+      load_slice(ch(g + 2), sA);
+      process(ch(g + 1), sB);
+      __syncthreads();
+      emit(g + 1);
+      if (!ONE_BARRIER) __syncthreads();
+    }
+  } else {
+    const int G = (count + GW - 1) / GW;
+    Slice sA;
+    load_slice(ch(0), sA);
+    emit(-1);
+    for (int g = 0; g < G; ++g) {
+      process(ch(g), sA);
+      load_slice(ch(g + 1), sA);
+      __syncthreads();
+      emit(g);
+      if (!ONE_BARRIER) __syncthreads();
+    }
+  }
+  __syncthreads();  // the ring becomes the reduction buffer
+
+  red_s[t] = static_cast<double>(psum);
+  red_m[t] = pmax;
+  __syncthreads();
+#pragma unroll
+  for (int s = NT / 2; s > 0; s >>= 1) {
+    if (t < s) {
+      red_s[t] += red_s[t + s];
+      red_m[t] = fmaxf(red_m[t], red_m[t + s]);
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    publish(&a.partials[2 * blk], red_s[0]);
+    publish(&a.partials[2 * blk + 1], static_cast<double>(red_m[0]));
+    last_flag = arrive_last(dev, static_cast<uint32_t>(blk), static_cast<uint32_t>(nblk));
+  }
+  __syncthreads();
+  if (!last_flag) return;
+  finalize_step<NT>(a, dev, nblk, scale, cur, red_s, red_m);
+}
+
 template <typename T, int R, int TX, int TY, int NT>
 __global__ __launch_bounds__(NT) void step_single(StepArgs a) {
   const int n = a.tiles_x * a.tiles_y * a.chunks;
@@ -870,6 +1471,40 @@ void stream_batch(const StepArgs* __restrict__ jobs,
   stream_body<T, R, TY, WAVES, NBUF>(a, g - first[j], n);
 }
 
+template <typename T, int R, int TY, int WAVES, int NBUF>
+__global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(stream_waves_per_eu<WAVES>())))
+void stream2_single(StepArgs a, ShiftArgs tab) {
+  const int n = a.tiles_x * a.tiles_y * a.chunks;
+  stream2_body<T, R, TY, WAVES, NBUF>(a, a.table ? a.table : tab.e, xcd_remap(blockIdx.x, n), n);
+}
+
+template <typename T, int R, int TY, int WAVES, int NBUF>
+__global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(stream_waves_per_eu<WAVES>())))
+void stream2_batch(const StepArgs* __restrict__ jobs, const int32_t* __restrict__ first, int njobs, int total) {
+  const int g = xcd_remap(blockIdx.x, total);
+  const int j = find_job(first, njobs, g);
+  const StepArgs& a = jobs[j];
+  const int n = a.tiles_x * a.tiles_y * a.chunks;
+  stream2_body<T, R, TY, WAVES, NBUF>(a, a.table, g - first[j], n);
+}
+
+template <typename T, int R, int TY, int WAVES, int NBUF>
+__global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(stream_waves_per_eu<WAVES>())))
+void stream3_single(StepArgs a, ShiftArgs tab) {
+  const int n = a.tiles_x * a.tiles_y * a.chunks;
+  stream3_body<T, R, TY, WAVES, NBUF>(a, a.table ? a.table : tab.e, xcd_remap(blockIdx.x, n), n);
+}
+
+template <typename T, int R, int TY, int WAVES, int NBUF>
+__global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(stream_waves_per_eu<WAVES>())))
+void stream3_batch(const StepArgs* __restrict__ jobs, const int32_t* __restrict__ first, int njobs, int total) {
+  const int g = xcd_remap(blockIdx.x, total);
+  const int j = find_job(first, njobs, g);
+  const StepArgs& a = jobs[j];
+  const int n = a.tiles_x * a.tiles_y * a.chunks;
+  stream3_body<T, R, TY, WAVES, NBUF>(a, a.table, g - first[j], n);
+}
+
 template <typename T, int R, int TX, int TY, int NT>
 hipError_t launch_tiled(const StepArgs* single, const StepArgs* jobs, const int32_t* first, int njobs, int total,
                         hipStream_t s) {
@@ -896,14 +1531,61 @@ hipError_t launch_stream(const StepArgs* single, const StepArgs* jobs, const int
   return hipGetLastError();
 }
 
+template <typename T, int R, int TY, int WAVES, int NBUF>
+hipError_t launch_stream2(const StepArgs* single, const ShiftArgs* tab, const StepArgs* jobs, const int32_t* first,
+                          int njobs, int total, hipStream_t s) {
+  if (single) {
+    const int n = single->tiles_x * single->tiles_y * single->chunks;
+    if (!single->table && !tab) return hipErrorInvalidValue;
+    static const ShiftArgs kNone = {};
+    hipLaunchKernelGGL((stream2_single<T, R, TY, WAVES, NBUF>), dim3(n), dim3(64 * WAVES), 0, s, *single,
+                       single->table ? kNone : *tab);
+  } else {
+    hipLaunchKernelGGL((stream2_batch<T, R, TY, WAVES, NBUF>), dim3(total), dim3(64 * WAVES), 0, s, jobs, first, njobs,
+                       total);
+  }
+  return hipGetLastError();
+}
+
+template <typename T, int R, int TY, int WAVES, int NBUF>
+hipError_t launch_stream3(const StepArgs* single, const ShiftArgs* tab, const StepArgs* jobs, const int32_t* first,
+                          int njobs, int total, hipStream_t s) {
+  if (single) {
+    const int n = single->tiles_x * single->tiles_y * single->chunks;
+    if (!single->table && !tab) return hipErrorInvalidValue;
+    static const ShiftArgs kNone = {};
+    hipLaunchKernelGGL((stream3_single<T, R, TY, WAVES, NBUF>), dim3(n), dim3(64 * WAVES), 0, s, *single,
+                       single->table ? kNone : *tab);
+  } else {
+    hipLaunchKernelGGL((stream3_batch<T, R, TY, WAVES, NBUF>), dim3(total), dim3(64 * WAVES), 0, s, jobs, first, njobs,
+                       total);
+  }
+  return hipGetLastError();
+}
+
 // Instantiated launch shapes.  Tiled kernel: (TX, TY, NT).  Streaming
 // kernel: (TY rows per strip, waves, source-slice buffers).
 #define MCL_SHAPES(X) X(64, 16, 256) X(32, 16, 128)
 #define MCL_STREAM_SHAPES(X) X(4, 4, 2) X(8, 4, 2) X(12, 4, 2) X(16, 4, 2) X(4, 8, 1) X(8, 8, 1) X(16, 8, 1)
+// Variant-1 streaming kernel: (TY rows per strip, waves, source-slice buffers).
+#define MCL_STREAM2_SHAPES(X) X(4, 4, 2) X(8, 4, 2) X(4, 8, 1) X(8, 8, 1) X(4, 4, 1) X(8, 4, 1)
+// Variant-2 streaming kernel (rows per strip a multiple of the waves).
+#define MCL_STREAM3_SHAPES(X) X(4, 4, 2) X(8, 4, 2) X(4, 4, 1) X(8, 4, 1) X(8, 8, 1)
 
 template <typename T, int R>
-hipError_t dispatch_shape(const KernelShape& k, const StepArgs* single, const StepArgs* jobs, const int32_t* bj,
-                          int nj, int total, int max_theta, hipStream_t s) {
+hipError_t dispatch_shape(const KernelShape& k, const StepArgs* single, const ShiftArgs* tab, const StepArgs* jobs,
+                          const int32_t* bj, int nj, int total, int max_theta, hipStream_t s) {
+#define MCL_TRY_STREAM2(TY_, WV_, NB_)                                                     \
+  if (k.tx == 0 && k.variant == 1 && k.ty == TY_ && k.nt == 64 * WV_ && k.nbuf == NB_) \
+    return launch_stream2<T, R, TY_, WV_, NB_>(single, tab, jobs, bj, nj, total, s);
+  MCL_STREAM2_SHAPES(MCL_TRY_STREAM2)
+#undef MCL_TRY_STREAM2
+#define MCL_TRY_STREAM3(TY_, WV_, NB_)                                                     \
+  if (k.tx == 0 && k.variant == 2 && k.ty == TY_ && k.nt == 64 * WV_ && k.nbuf == NB_) \
+    return launch_stream3<T, R, TY_, WV_, NB_>(single, tab, jobs, bj, nj, total, s);
+  MCL_STREAM3_SHAPES(MCL_TRY_STREAM3)
+#undef MCL_TRY_STREAM3
+  if (k.variant != 0) return hipErrorInvalidValue;
 #define MCL_TRY_STREAM(TY_, WV_, NB_)                                     \
   if (k.tx == 0 && k.ty == TY_ && k.nt == 64 * WV_ && k.nbuf == NB_) \
     return launch_stream<T, R, TY_, WV_, NB_>(single, jobs, bj, nj, total, max_theta, s);
@@ -918,23 +1600,23 @@ hipError_t dispatch_shape(const KernelShape& k, const StepArgs* single, const St
 }
 
 template <typename T>
-hipError_t dispatch_radius(int radius, const KernelShape& k, const StepArgs* single, const StepArgs* jobs,
-                           const int32_t* bj, int nj, int total, int max_theta, hipStream_t s) {
+hipError_t dispatch_radius(int radius, const KernelShape& k, const StepArgs* single, const ShiftArgs* tab,
+                           const StepArgs* jobs, const int32_t* bj, int nj, int total, int max_theta, hipStream_t s) {
   switch (radius) {
-    case 1: return dispatch_shape<T, 1>(k, single, jobs, bj, nj, total, max_theta, s);
-    case 2: return dispatch_shape<T, 2>(k, single, jobs, bj, nj, total, max_theta, s);
-    case 3: return dispatch_shape<T, 3>(k, single, jobs, bj, nj, total, max_theta, s);
-    case 4: return dispatch_shape<T, 4>(k, single, jobs, bj, nj, total, max_theta, s);
+    case 1: return dispatch_shape<T, 1>(k, single, tab, jobs, bj, nj, total, max_theta, s);
+    case 2: return dispatch_shape<T, 2>(k, single, tab, jobs, bj, nj, total, max_theta, s);
+    case 3: return dispatch_shape<T, 3>(k, single, tab, jobs, bj, nj, total, max_theta, s);
+    case 4: return dispatch_shape<T, 4>(k, single, tab, jobs, bj, nj, total, max_theta, s);
     default: return hipErrorInvalidValue;
   }
 }
 
-hipError_t dispatch(int dtype, int radius, const KernelShape& k, const StepArgs* single, const StepArgs* jobs,
-                    const int32_t* bj, int nj, int total, int max_theta, hipStream_t s) {
+hipError_t dispatch(int dtype, int radius, const KernelShape& k, const StepArgs* single, const ShiftArgs* tab,
+                    const StepArgs* jobs, const int32_t* bj, int nj, int total, int max_theta, hipStream_t s) {
   switch (dtype) {
-    case 0: return dispatch_radius<float>(radius, k, single, jobs, bj, nj, total, max_theta, s);
-    case 1: return dispatch_radius<__bf16>(radius, k, single, jobs, bj, nj, total, max_theta, s);
-    case 2: return dispatch_radius<_Float16>(radius, k, single, jobs, bj, nj, total, max_theta, s);
+    case 0: return dispatch_radius<float>(radius, k, single, tab, jobs, bj, nj, total, max_theta, s);
+    case 1: return dispatch_radius<__bf16>(radius, k, single, tab, jobs, bj, nj, total, max_theta, s);
+    case 2: return dispatch_radius<_Float16>(radius, k, single, tab, jobs, bj, nj, total, max_theta, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -944,9 +1626,18 @@ hipError_t dispatch(int dtype, int radius, const KernelShape& k, const StepArgs*
 bool step_config_supported(int dtype, int radius, const KernelShape& k) {
   if (dtype < 0 || dtype > 2 || radius < 1 || radius > kMaxRadius) return false;
 #define MCL_HAS(TX_, TY_, NT_) \
-  if (k.tx == TX_ && k.ty == TY_ && k.nt == NT_) return true;
+  if (k.tx == TX_ && k.ty == TY_ && k.nt == NT_ && k.variant == 0) return true;
   MCL_SHAPES(MCL_HAS)
 #undef MCL_HAS
+#define MCL_HAS_STREAM2(TY_, WV_, NB_) \
+  if (k.tx == 0 && k.variant == 1 && k.ty == TY_ && k.nt == 64 * WV_ && k.nbuf == NB_) return true;
+  MCL_STREAM2_SHAPES(MCL_HAS_STREAM2)
+#undef MCL_HAS_STREAM2
+#define MCL_HAS_STREAM3(TY_, WV_, NB_) \
+  if (k.tx == 0 && k.variant == 2 && k.ty == TY_ && k.nt == 64 * WV_ && k.nbuf == NB_) return true;
+  MCL_STREAM3_SHAPES(MCL_HAS_STREAM3)
+#undef MCL_HAS_STREAM3
+  if (k.variant != 0) return false;
 #define MCL_HAS_STREAM(TY_, WV_, NB_) \
   if (k.tx == 0 && k.ty == TY_ && k.nt == 64 * WV_ && k.nbuf == NB_) return true;
   MCL_STREAM_SHAPES(MCL_HAS_STREAM)
@@ -954,14 +1645,15 @@ bool step_config_supported(int dtype, int radius, const KernelShape& k) {
   return false;
 }
 
-hipError_t launch_step(int dtype, int radius, const KernelShape& k, const StepArgs& a, hipStream_t s) {
-  return dispatch(dtype, radius, k, &a, nullptr, nullptr, 0, 0, a.n_theta, s);
+hipError_t launch_step(int dtype, int radius, const KernelShape& k, const StepArgs& a, const ShiftArgs* tab,
+                       hipStream_t s) {
+  return dispatch(dtype, radius, k, &a, tab, nullptr, nullptr, 0, 0, a.n_theta, s);
 }
 
 hipError_t launch_step_batch(int dtype, int radius, const KernelShape& k, const StepArgs* jobs_dev,
                              const int32_t* first_dev, int32_t njobs, int32_t total_blocks, int32_t max_theta,
                              hipStream_t s) {
-  return dispatch(dtype, radius, k, nullptr, jobs_dev, first_dev, njobs, total_blocks, max_theta, s);
+  return dispatch(dtype, radius, k, nullptr, nullptr, jobs_dev, first_dev, njobs, total_blocks, max_theta, s);
 }
 
 }  // namespace mcl

@@ -30,7 +30,8 @@ ABI_SYMBOLS = [
     "mcl_apply_scan", "mcl_normalize", "mcl_read_belief", "mcl_export_belief", "mcl_scan_sqdist",
     "mcl_get_info", "mcl_step_batch", "mcl_batch_workspace_bytes", "mcl_sample_cells",
     "mcl_apply_scan_sampled", "mcl_dither", "mcl_match_workspace_bytes", "mcl_best_match",
-    "mcl_difficulty",
+    "mcl_difficulty", "mcl_batch_create", "mcl_batch_step", "mcl_batch_counts", "mcl_batch_destroy",
+    "mcl_export_scalars", "mcl_apply_scan_batch",
 ]
 
 
@@ -43,7 +44,7 @@ class MapDesc(ctypes.Structure):
 class Params(ctypes.Structure):
     _fields_ = [("n_theta", c_int32), ("sigma_xy_cells", c_double), ("sigma_theta_bins", c_double),
                 ("radius_xy", c_int32), ("radius_theta", c_int32), ("storage", c_int32),
-                ("flags", c_uint32), ("sigma_lateral_cells", c_double)]
+                ("flags", c_uint32), ("sigma_lateral_cells", c_double), ("launch_shape", c_int32 * 7)]
 
 
 class Pose(ctypes.Structure):
@@ -129,6 +130,18 @@ def load_library(path: str = _LIB_PATH):
                                    c_void_p, c_size_t, c_void_p]
     lib.mcl_difficulty.restype = c_int
     lib.mcl_difficulty.argtypes = [c_void_p, c_void_p, c_void_p, c_int32, c_double, c_void_p]
+    lib.mcl_batch_create.restype = c_int
+    lib.mcl_batch_create.argtypes = [c_int32, c_void_p, c_size_t, c_void_p, POINTER(c_void_p)]
+    lib.mcl_batch_step.restype = c_int
+    lib.mcl_batch_step.argtypes = [c_void_p, POINTER(c_void_p), c_void_p, c_int32]
+    lib.mcl_batch_counts.restype = c_int
+    lib.mcl_batch_counts.argtypes = [c_void_p, POINTER(c_int64), POINTER(c_int64)]
+    lib.mcl_apply_scan_batch.restype = c_int
+    lib.mcl_apply_scan_batch.argtypes = [POINTER(c_void_p), c_void_p, c_int32, c_void_p, c_int32]
+    lib.mcl_export_scalars.restype = c_int
+    lib.mcl_export_scalars.argtypes = [c_void_p, c_void_p]
+    lib.mcl_batch_destroy.restype = None
+    lib.mcl_batch_destroy.argtypes = [c_void_p]
     _lib = lib
     return lib
 
@@ -149,9 +162,11 @@ def _stream_handle(stream):
 
 
 def _params(n_theta=1, sigma_xy=0.0, sigma_theta=0.0, radius_xy=-1, radius_theta=-1, storage="f32",
-            flags=DEFAULT_FLAGS, sigma_lateral=0.0) -> Params:
+            flags=DEFAULT_FLAGS, sigma_lateral=0.0, launch_shape=None) -> Params:
+    shape = (c_int32 * 7)(*(list(launch_shape or []) + [0] * 7)[:7])
     return Params(int(n_theta), float(sigma_xy), float(sigma_theta), int(radius_xy), int(radius_theta),
-                  DTYPES[storage] if isinstance(storage, str) else int(storage), int(flags), float(sigma_lateral))
+                  DTYPES[storage] if isinstance(storage, str) else int(storage), int(flags), float(sigma_lateral),
+                  shape)
 
 
 class Map:
@@ -196,14 +211,16 @@ class Filter:
     """One belief tensor on the GPU (init_belief)."""
 
     def __init__(self, map: Map, n_theta, sigma_theta, *, radius_theta=-1, storage="f32", init=None,
-                 theta0=0.0, stream=None, sigma_lateral=0.0):
+                 theta0=0.0, stream=None, sigma_lateral=0.0, launch_shape=None):
+        """launch_shape (testing and tuning only): the step kernel's launch shape, as
+        mcl_params.launch_shape; None lets the library choose."""
         import torch
         lib = load_library()
         self.map = map
         self.n_theta = int(n_theta)
         self.storage = storage
         self.params = _params(n_theta, map.sigma_xy, sigma_theta, map.radius_xy, radius_theta, storage,
-                              map.flags, sigma_lateral)
+                              map.flags, sigma_lateral, launch_shape)
         nbytes = lib.mcl_filter_workspace_bytes(map.handle, byref(self.params))
         if nbytes == 0:
             _check(lib.mcl_init_belief(map.handle, byref(self.params), None, 0, None, None, 0.0,
@@ -216,6 +233,9 @@ class Filter:
             assert self._init.shape == (self.n_theta, map.height, map.width)
             init_ptr = self._init.ctypes.data
         self.stream = stream
+        # the torch stream the filter's work runs on; outputs handed back as
+        # tensors are ordered after it on the caller's current stream
+        self._tstream = stream if stream is not None else torch.cuda.current_stream()
         h = c_void_p()
         _check(lib.mcl_init_belief(map.handle, byref(self.params), c_void_p(self.workspace.data_ptr()), nbytes,
                                    _stream_handle(stream), init_ptr, float(theta0), byref(h)))
@@ -260,13 +280,31 @@ class Filter:
         bm = torch.empty((self.map.height, self.map.width), dtype=torch.float32, device="cuda") if with_map else None
         _check(_lib.mcl_export_belief(self.handle, c_void_p(out.data_ptr()),
                                       c_void_p(bm.data_ptr()) if bm is not None else None))
+        self._order_after()
         return (out, bm) if with_map else out
+
+    def _order_after(self):
+        """Order the caller's current stream after the work enqueued on the filter's stream."""
+        import torch
+        cur = torch.cuda.current_stream()
+        if cur != self._tstream:
+            cur.wait_stream(self._tstream)
+
+    def export_scalars(self, out=None):
+        """Device float64 tensor [log_norm, status] as of the work enqueued so far (async)."""
+        import torch
+        if out is None:
+            out = torch.empty(2, dtype=torch.float64, device="cuda")
+        _check(_lib.mcl_export_scalars(self.handle, c_void_p(out.data_ptr())))
+        self._order_after()
+        return out
 
     def scan_sqdist(self, ranges_m):
         import torch
         z = np.ascontiguousarray(ranges_m, dtype=np.float32)
         out = torch.empty((self.n_theta, self.map.height, self.map.width), dtype=torch.int32, device="cuda")
         _check(_lib.mcl_scan_sqdist(self.handle, z.ctypes.data, len(z), c_void_p(out.data_ptr())))
+        self._order_after()
         return out
 
     def sample_cells(self, n_samples, out=None):
@@ -275,6 +313,7 @@ class Filter:
         if out is None:
             out = torch.empty((self.map.height, self.map.width), dtype=torch.uint8, device="cuda")
         _check(_lib.mcl_sample_cells(self.handle, int(n_samples), c_void_p(out.data_ptr())))
+        self._order_after()
         return out
 
     def apply_scan_sampled(self, ranges_m, sigma_m, mask):
@@ -303,6 +342,17 @@ def step_odometry(f: Filter, u, v, w):
 
 def apply_scan(f: Filter, ranges_m, sigma_m):
     f.apply_scan(ranges_m, sigma_m)
+
+
+def apply_scan_batch(filters, ranges_m, sigma_m):
+    """Scan updates of several filters of one map (n scans, one std-dev each) in shared launches."""
+    if not filters:
+        return
+    arr = (c_void_p * len(filters))(*[f.handle.value for f in filters])
+    z = np.ascontiguousarray(ranges_m, dtype=np.float32)
+    sig = np.ascontiguousarray(np.broadcast_to(np.asarray(sigma_m, np.float64), (len(filters),)))
+    assert z.ndim == 2 and z.shape[0] == len(filters)
+    _check(load_library().mcl_apply_scan_batch(arr, z.ctypes.data, z.shape[1], sig.ctypes.data, len(filters)))
 
 
 def normalize(f: Filter) -> float:
@@ -393,3 +443,40 @@ def step_batch(filters, uvw, workspace: BatchWorkspace, stream=None):
     u = np.ascontiguousarray(uvw, dtype=np.float64)
     _check(load_library().mcl_step_batch(arr, u.ctypes.data, len(filters), c_void_p(workspace.tensor.data_ptr()),
                                          workspace.nbytes, _stream_handle(stream)))
+
+
+class BatchRunner:
+    """Graph-replayed batched steps (mcl_batch_*): one HIP graph per launch
+    structure, replayed while the set of filters keeps its shape.  Runs on
+    `stream` (default: the current stream), which must not be the default
+    NULL stream; the filters must be driven on the same stream."""
+
+    def __init__(self, max_filters, stream=None):
+        import torch
+        lib = load_library()
+        self.max_filters = int(max_filters)
+        n = lib.mcl_batch_workspace_bytes(self.max_filters)
+        if n == 0:
+            raise MclError(EINVAL, "batch size out of range")
+        self.workspace = torch.empty(n, dtype=torch.uint8, device="cuda")
+        h = c_void_p()
+        _check(lib.mcl_batch_create(self.max_filters, c_void_p(self.workspace.data_ptr()), n,
+                                    _stream_handle(stream), byref(h)))
+        self.handle = h
+
+    def step(self, filters, uvw):
+        """One odometry step for each filter; uvw: (n, 3) robot-frame increments."""
+        arr = (c_void_p * len(filters))(*[f.handle.value for f in filters])
+        u = np.ascontiguousarray(uvw, dtype=np.float64)
+        _check(_lib.mcl_batch_step(self.handle, arr, u.ctypes.data, len(filters)))
+
+    def counts(self):
+        """(graph captures, graph replays) so far."""
+        c, r = c_int64(), c_int64()
+        _check(_lib.mcl_batch_counts(self.handle, byref(c), byref(r)))
+        return c.value, r.value
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.mcl_batch_destroy(self.handle)
+            self.handle = None

@@ -3,23 +3,30 @@
 Requests (a map, a heading count, a storage type, an odometry stream and
 optional scans) arrive over time.  The server admits a request as soon as its
 filter workspace fits the HBM budget and a slot is free; every iteration it
-advances *all* active filters by one odometry step with one batched launch per
-kernel variant (mcl_step_batch: filters of different grid sizes and heading
-counts share a launch), applies the scans that are due, and retires finished
-requests, which frees their memory for queued ones.  Work of requests that
-arrive while others run therefore overlaps on the device.
+advances *all* active filters by one odometry step through a graph-replayed
+batch (mcl_batch_step: the step parameters go into a pinned slot, a HIP
+graph per launch structure copies them to the device and runs one launch per
+kernel group, filters of any grid size and heading count sharing a launch),
+applies the due scans of the filters of each map in shared launches
+(mcl_apply_scan_batch), and retires finished requests, whose readout is
+exported asynchronously and whose memory goes to queued requests.  Work of
+requests that arrive while others run therefore overlaps on the device, and
+the host never waits for the stream except to bound the iterations in
+flight.
 
 Each filter's result is bitwise identical to running it alone: the batched
-kernel gives every filter its own workgroups, reduction order and final
-reduction.  Latency is measured with HIP events around each iteration on the
-launch stream; throughput is total states x steps over the wall-clock span.
+kernels give every filter its own workgroups, reduction order and final
+reduction.  Latency is per request step, from the host time its iteration
+was enqueued to the completion of that iteration on the device (HIP events,
+placed on the host clock by a reference event); throughput is total
+states x steps over the wall-clock span.
 """
 
 from __future__ import annotations
 
 import dataclasses
 import time
-from collections import deque
+from collections import defaultdict, deque
 
 import numpy as np
 
@@ -47,14 +54,30 @@ class Result:
     steps: int
     states: int
     belief: np.ndarray | None
-    pose: tuple
+    pose: tuple | None
     log_norm: float
     degenerate: bool = False   # a step removed all probability mass (belief kept, Sec. III-A)
 
 
+class _Draining:
+    """A retired filter's asynchronous readout (belief and scalars to pinned host memory)."""
+
+    def __init__(self, torch, f, want_belief):
+        self.belief = None
+        dev_scalars = f.export_scalars()
+        self.scalars = torch.empty(2, dtype=torch.float64, pin_memory=True)
+        self.scalars.copy_(dev_scalars, non_blocking=True)
+        if want_belief:
+            dev_b = f.export_belief()
+            self.belief = torch.empty(dev_b.shape, dtype=torch.float32, pin_memory=True)
+            self.belief.copy_(dev_b, non_blocking=True)
+        self.event = torch.cuda.Event()
+        self.event.record()
+
+
 class Server:
     def __init__(self, maps: dict, hbm_budget_bytes: int, max_active: int = 256, keep_beliefs: bool = False,
-                 max_inflight: int = 4):
+                 max_inflight: int = 3):
         import torch
         self.torch = torch
         self.maps = maps
@@ -62,8 +85,10 @@ class Server:
         self.max_active = int(max_active)
         self.keep_beliefs = keep_beliefs
         self.max_inflight = max_inflight
-        self.ws = mcl.BatchWorkspace(self.max_active)
-        self.stream = torch.cuda.current_stream()
+        # a stream of its own: graphs cannot be captured on the default stream
+        self.stream = torch.cuda.Stream()
+        with torch.cuda.stream(self.stream):
+            self.runner = mcl.BatchRunner(self.max_active)
 
     def _workspace_bytes(self, req: Request) -> int:
         m = self.maps[req.map_key]
@@ -72,18 +97,45 @@ class Server:
 
     def run(self, requests):
         """Serve `requests` (arrival times relative to the start); returns (results, stats)."""
+        with self.torch.cuda.stream(self.stream):
+            return self._run(requests)
+
+    def _run(self, requests):
         torch = self.torch
         pending = deque(sorted(requests, key=lambda r: r.arrival_s))
         active = []       # [request, filter, position, admitted_s, bytes]
         used = 0
         results = {}
-        lat_events = []   # (start event, end event, filter-steps in the iteration)
+        draining = []     # (request, _Draining, admitted_s, steps, states)
+        iters = []        # (host enqueue time, completion event, filter-steps in the iteration)
         inflight = deque()
         waits = []
         peak_used = 0
         peak_active = 0
-        t0 = time.perf_counter()
         states_steps = 0
+        ref = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ref.record(self.stream)
+
+        def finish_drained(block):
+            still = []
+            for req, d, adm, steps, states in draining:
+                if block:
+                    d.event.synchronize()
+                if not d.event.query():
+                    still.append((req, d, adm, steps, states))
+                    continue
+                b = d.belief.numpy().copy() if d.belief is not None else None
+                pose = None
+                if b is not None:
+                    k, j, i = np.unravel_index(int(np.argmax(b)), b.shape)  # lowest flat index wins ties
+                    pose = (int(k), int(j), int(i))
+                ln, status = float(d.scalars[0]), int(d.scalars[1])
+                results[req.rid] = Result(req.rid, adm, time.perf_counter() - t0, steps, states, b, pose, ln,
+                                          status == mcl.EDEGENERATE)
+            draining[:] = still
+
         while pending or active:
             now = time.perf_counter() - t0
             # admission: FIFO, by memory budget and slots
@@ -102,55 +154,63 @@ class Server:
                 peak_active = max(peak_active, len(active))
                 waits.append(now - req.arrival_s)
             if not active:
+                finish_drained(False)
                 if pending:
                     time.sleep(max(0.0, min(pending[0].arrival_s - now, 0.01)))
                 continue
             # one iteration: every active filter advances one step
+            t_enq = time.perf_counter() - t0
             filters = [a[1] for a in active]
             uvw = np.stack([a[0].odometry[a[2]] for a in active])
-            e0 = torch.cuda.Event(enable_timing=True)
-            e1 = torch.cuda.Event(enable_timing=True)
-            e0.record(self.stream)
-            mcl.step_batch(filters, uvw, self.ws)
+            self.runner.step(filters, uvw)
+            due = defaultdict(list)
             for a in active:
                 z = a[0].scans.get(a[2])
                 if z is not None:
-                    a[1].apply_scan(z, a[0].scan_sigma_m)
-            e1.record(self.stream)
-            lat_events.append((e0, e1, len(active)))
-            inflight.append(e1)
+                    due[(a[0].map_key, a[0].scan_sigma_m)].append((a[1], z))
+            for (_, sig), fz in due.items():
+                mcl.apply_scan_batch([f for f, _ in fz], np.stack([z for _, z in fz]), sig)
+            done = torch.cuda.Event(enable_timing=True)
+            done.record(self.stream)
+            iters.append((t_enq, done, len(active)))
+            inflight.append(done)
             if len(inflight) > self.max_inflight:
                 inflight.popleft().synchronize()
             still = []
             for a in active:
                 a[2] += 1
                 req, f = a[0], a[1]
-                states_steps += f.map.width * f.map.height * req.n_theta
+                states = f.map.width * f.map.height * req.n_theta
+                states_steps += states
                 if a[2] == len(req.odometry):
-                    b, pose, ln, degen = _final_readout(f, self.keep_beliefs)
-                    results[req.rid] = Result(req.rid, a[3], time.perf_counter() - t0, a[2],
-                                              f.map.width * f.map.height * req.n_theta,
-                                              b, pose, ln, degen)
+                    draining.append((req, _Draining(torch, f, self.keep_beliefs), a[3], a[2], states))
                     used -= a[4]
-                    del f
                     a[1] = None
+                    del f
                 else:
                     still.append(a)
             active = still
+            finish_drained(False)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
-        per_step = []
-        for e0, e1, n in lat_events:
-            per_step.extend([e0.elapsed_time(e1)] * n)
-        per_step = np.array(per_step) if per_step else np.zeros(1)
+        finish_drained(True)
+        lat = []
+        for t_enq, ev, n in iters:
+            done_s = ref.elapsed_time(ev) * 1e-3
+            lat.extend([max(0.0, done_s - t_enq) * 1e3] * n)
+        lat = np.array(lat) if lat else np.zeros(1)
+        captures, replays = self.runner.counts()
         stats = {
             "requests": len(results),
             "wall_s": wall,
             "states_steps": states_steps,
             "states_steps_per_s": states_steps / wall if wall > 0 else 0.0,
-            "step_latency_ms_p50": float(np.percentile(per_step, 50)),
-            "step_latency_ms_p99": float(np.percentile(per_step, 99)),
-            "iterations": len(lat_events),
+            "step_latency_ms_p50": float(np.percentile(lat, 50)),
+            "step_latency_ms_p99": float(np.percentile(lat, 99)),
+            "latency": "per request step: host enqueue of its iteration to the iteration's completion on the GPU",
+            "iterations": len(iters),
+            "graph_captures": captures,
+            "graph_replays": replays,
             "admission_wait_s_p50": float(np.percentile(waits, 50)) if waits else 0.0,
             "admission_wait_s_p99": float(np.percentile(waits, 99)) if waits else 0.0,
             "degenerate_requests": sum(1 for r in results.values() if r.degenerate),
@@ -159,22 +219,6 @@ class Server:
             "budget_bytes": self.budget,
         }
         return results, stats
-
-
-def _final_readout(f, want_belief):
-    """Belief, argmax pose, log-normaliser and the degenerate flag of a filter.
-
-    A filter whose mass was all removed by some step reports EDEGENERATE; its
-    readout (the last belief that had mass) is still returned.
-    """
-    try:
-        b, pose, _, ln = f.read_belief(want_belief=want_belief)
-        return b, pose.as_tuple(), ln, False
-    except mcl.MclError as e:
-        if e.status != mcl.EDEGENERATE:
-            raise
-        b, pose, _, ln = e.readout
-        return b, pose.as_tuple(), ln, True
 
 
 def run_alone(maps, req: Request, keep_belief=True):
@@ -187,4 +231,11 @@ def run_alone(maps, req: Request, keep_belief=True):
         z = req.scans.get(t)
         if z is not None:
             f.apply_scan(z, req.scan_sigma_m)
-    return _final_readout(f, keep_belief)
+    try:
+        b, pose, _, ln = f.read_belief(want_belief=keep_belief)
+        return b, pose.as_tuple(), ln, False
+    except mcl.MclError as e:
+        if e.status != mcl.EDEGENERATE:
+            raise
+        b, pose, _, ln = e.readout
+        return b, pose.as_tuple(), ln, True

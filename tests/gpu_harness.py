@@ -37,11 +37,11 @@ def oracle_params(n_theta, cell, sxy, sth, rxy=-1, rth=-1, flags=3, sigma_latera
 
 
 def make_gpu(occ, cell, n_theta, sxy, sth, rxy=-1, rth=-1, storage="f32", flags=3, init=None, theta0=0.0,
-             range_table=None, max_range_m=0.0, sigma_lateral=0.0):
+             range_table=None, max_range_m=0.0, sigma_lateral=0.0, launch_shape=None):
     from paper_1910_00572_amd import mcl
     m = mcl.Map(occ, cell, sxy, radius_xy=rxy, flags=flags, range_table=range_table, max_range_m=max_range_m)
     f = mcl.Filter(m, n_theta, sth, radius_theta=rth, storage=storage, init=init, theta0=theta0,
-                   sigma_lateral=sigma_lateral)
+                   sigma_lateral=sigma_lateral, launch_shape=launch_shape)
     return m, f
 
 

@@ -39,9 +39,9 @@ def test_struct_layouts_match_header(tmp_path):
 #include <stdio.h>
 #include "mcl.h"
 int main(void) {
-  printf("%zu %zu %zu %zu %zu %zu %zu\\n", sizeof(mcl_map_desc), sizeof(mcl_params),
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(mcl_map_desc), sizeof(mcl_params),
          offsetof(mcl_params, sigma_lateral_cells), sizeof(mcl_pose), offsetof(mcl_info, steps),
-         offsetof(mcl_info, belief_device), sizeof(mcl_info));
+         offsetof(mcl_info, belief_device), sizeof(mcl_info), offsetof(mcl_params, launch_shape));
   return 0;
 }
 """)
@@ -51,7 +51,7 @@ int main(void) {
     got = [int(x) for x in subprocess.check_output([str(exe)]).split()]
     assert got == [ctypes.sizeof(mcl.MapDesc), ctypes.sizeof(mcl.Params), mcl.Params.sigma_lateral_cells.offset,
                    ctypes.sizeof(mcl.Pose), mcl.Info.steps.offset, mcl.Info.belief_device.offset,
-                   ctypes.sizeof(mcl.Info)]
+                   ctypes.sizeof(mcl.Info), mcl.Params.launch_shape.offset]
 
 
 def test_argument_errors_before_any_device_work():

@@ -20,10 +20,10 @@ pytestmark = [pytest.mark.gpu, needs_gpu]
 
 
 def _run_pair(occ, cell, n_theta, sxy, sth, odo, *, rxy=-1, rth=-1, flags=3, check_every=1, tag="",
-              sigma_lateral=0.0, storage="f32"):
+              sigma_lateral=0.0, storage="f32", launch_shape=None):
     say(f"[parity] {tag} map={occ.shape} T={n_theta} sxy={sxy} sth={sth} steps={len(odo)} flags={flags}")
     _, f = make_gpu(occ, cell, n_theta, sxy, sth, rxy, rth, flags=flags, sigma_lateral=sigma_lateral,
-                    storage=storage)
+                    storage=storage, launch_shape=launch_shape)
     p = oracle_params(n_theta, cell, sxy, sth, rxy, rth, flags, sigma_lateral=sigma_lateral)
     st = O.init_uniform(occ, n_theta)
     M = O.free_mask(occ)
@@ -67,14 +67,34 @@ def test_multi_tile_map_with_theta_chunks():
     _run_pair(occ, 0.1, 40, 1.0, 1.0, odo, check_every=5, tag="multitile")
 
 
-@pytest.mark.parametrize("shape", ["64,16,256,0", "32,16,128,0", "0,4,256,1,2", "0,8,256,1,2", "0,12,256,2,2",
-                                   "0,16,256,1,2", "0,4,512,2,1", "0,8,512,1,1", "0,16,512,1,1"])
-def test_every_kernel_shape(shape, monkeypatch):
+# every instantiated launch shape: (tile width, rows, threads, heading chunks,
+# slice buffers, variant, strip alignment); tile width 0 = streaming kernels
+KERNEL_SHAPES = [
+    (64, 16, 256, 0), (32, 16, 128, 0),
+    (0, 4, 256, 1, 2), (0, 8, 256, 1, 2), (0, 12, 256, 2, 2), (0, 16, 256, 1, 2), (0, 4, 512, 2, 1),
+    (0, 8, 512, 1, 1), (0, 16, 512, 1, 1), (0, 16, 512, 1, 1, 0, 4),
+    (0, 4, 256, 1, 2, 1), (0, 4, 256, 1, 2, 1, 4), (0, 8, 256, 1, 2, 1), (0, 4, 256, 2, 2, 1),
+    (0, 4, 512, 1, 1, 1), (0, 8, 512, 2, 1, 1), (0, 4, 256, 1, 1, 1), (0, 8, 256, 1, 1, 1),
+    (0, 4, 256, 1, 2, 2), (0, 8, 256, 1, 2, 2), (0, 4, 256, 2, 2, 2), (0, 4, 256, 1, 1, 2),
+    (0, 8, 256, 1, 1, 2), (0, 8, 512, 1, 1, 2),
+]
+
+
+@pytest.mark.parametrize("shape", KERNEL_SHAPES, ids=lambda s: ",".join(map(str, s)))
+def test_every_kernel_shape(shape):
     # the launch shape is chosen when the filter is created; each one must match the oracle
-    monkeypatch.setenv("MCL_STEP_SHAPE", shape)
     occ = bsp_rooms(150, 70, seed=9)
     odo = random_odometry(12, seed=10, max_step_m=0.2) - np.array([0.1, 0.1, 0.0])
-    _run_pair(occ, 0.1, 40, 1.0, 1.0, odo, check_every=4, tag=f"shape {shape}")
+    _run_pair(occ, 0.1, 40, 1.0, 1.0, odo, check_every=4, tag=f"shape {shape}", launch_shape=shape)
+
+
+def test_unknown_launch_shape_is_rejected():
+    from paper_1910_00572_amd import mcl
+    occ = bsp_rooms(40, 40, seed=11)
+    for bad in [(0, 5, 256, 1, 2), (48, 16, 256, 0), (0, 4, 256, 1, 2, 3), (0, 4, 256, 1, 2, 0, 12)]:
+        with pytest.raises(mcl.MclError) as ei:
+            make_gpu(occ, 0.1, 8, 0.7, 0.7, launch_shape=bad)
+        assert ei.value.status == mcl.EINVAL
 
 
 @pytest.mark.parametrize("case", [
@@ -256,3 +276,14 @@ def test_cfg2_full_size_single_step_parity():
     say(f"[parity] cfg2 one-step peak-normalised error {err:.3e}")
     assert err <= FP32_PEAK_TOL
     assert in_tie_set(pose2.as_tuple(), ref.B, FP32_TIE_TAU)
+
+
+def test_cfg2_full_size_trajectory_from_the_uniform_start():
+    # 512x512 floor plan at 0.05 m, 72 bins, sigma 1 cell / 1 bin, the smooth
+    # trajectory of the headline workload from the uniform start: 50 steps at
+    # the launch shape the benchmark uses, every 10th step checked against the
+    # oracle's own trajectory (peak-normalised max-abs <= 1e-5, argmax in the
+    # tie set, log-normaliser).
+    occ = rooms_and_corridors(512, 512, seed=3)
+    _, odo = smooth_trajectory(occ, 0.05, 50, seed=4)
+    _run_pair(occ, 0.05, 72, 1.0, 1.0, odo[:50], check_every=10, tag="cfg2 trajectory")

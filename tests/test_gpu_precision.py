@@ -115,3 +115,60 @@ def test_full_size_mixed_precision_one_step_and_argmax_agreement():
     say(f"[precision] full size FP32 one-step peak-normalised error {err:.3e}")
     assert err <= 1e-5
     assert in_tie_set(pose.as_tuple(), ref.B, 1e-6)
+
+
+@pytest.mark.parametrize("storage", ["bf16", "f16"])
+def test_reduced_precision_resume_of_a_sum_one_belief(storage):
+    # 300 x 300 cells x 256 headings: a sum-one belief of 23 M states holds
+    # values near 4e-8, below FP16's smallest subnormal (6e-8).  Resuming a
+    # 16-bit filter from such an export must keep it (the upload stores the
+    # belief max-scaled, as every step does), to the 16-bit storage's
+    # precision: L1 <= 1e-2 and the argmax in the tie set.
+    occ = bsp_rooms(300, 300, seed=47)
+    odo = random_odometry(3, seed=48)
+    _, f = make_gpu(occ, 0.1, 256, 0.7, 0.7)
+    for u, v, w in odo:
+        f.step_odometry(u, v, w)
+    b, _, th, _ = f.read_belief()
+    assert np.median(b[b > 0]) < 6e-8
+    _, g = make_gpu(occ, 0.1, 256, 0.7, 0.7, storage=storage, init=b, theta0=th)
+    b2, pose, th2, ln2 = g.read_belief()
+    ref = b.astype(np.float64)
+    l1 = float(np.abs(b2.astype(np.float64) - ref).sum())
+    say(f"[precision] {storage} resume of a sum-one FP32 export: L1 {l1:.3e}")
+    assert l1 <= L1_TOL
+    assert in_tie_set(pose.as_tuple(), ref, TIE_TAU)
+    assert th2 == th and ln2 == 0.0
+
+
+def test_reduced_precision_at_the_large_map_shapes():
+    # BF16 and FP16 storage through the launch shapes large maps use (16-row
+    # strips, 8 waves, one slice buffer, 4-byte strip alignment; and 8-row
+    # strips), 128 heading bins, 200 steps against the FP64 oracle: L1 <= 1e-2
+    # and the argmax in the tie set at every 20th step.
+    occ = rooms_and_corridors(128, 128, seed=49)
+    _, odo = smooth_trajectory(occ, 0.05, 200, seed=50)
+    n_theta = 128
+    p = oracle_params(n_theta, 0.05, 1.0, 1.0)
+    from paper_1910_00572_amd import mcl
+    m = mcl.Map(occ, 0.05, 1.0)
+    shapes = [(0, 16, 512, 1, 1, 0, 4), (0, 8, 512, 1, 1, 0, 4)]
+    gpu = {(st, sh): mcl.Filter(m, n_theta, 1.0, storage=st, launch_shape=sh)
+           for st in ("bf16", "f16") for sh in shapes}
+    st_o = O.init_uniform(occ, n_theta)
+    M = O.free_mask(occ)
+    worst = {k: 0.0 for k in gpu}
+    for t, (u, v, w) in enumerate(odo):
+        for f in gpu.values():
+            f.step_odometry(u, v, w)
+        st_o = O.step(st_o, occ, p, u, v, w, M=M)
+        if t % 20 == 19:
+            for key, f in gpu.items():
+                b, pose, _, ln = f.read_belief()
+                l1 = l1_err(b, st_o.B)
+                worst[key] = max(worst[key], l1)
+                assert l1 <= L1_TOL, f"{key} step {t}: L1 {l1:.3e}"
+                assert in_tie_set(pose.as_tuple(), st_o.B, TIE_TAU), f"{key} step {t}: argmax {pose.as_tuple()}"
+                assert abs(ln - st_o.log_norm) < 1e-2
+    for key, wv in worst.items():
+        say(f"[precision] {key}: worst L1 over 200 steps {wv:.3e}")
