@@ -32,7 +32,7 @@ from .filter import (
     belief_map,
     argmax_pose,
 )
-from .scan import quantize_ranges, beam_offsets, scan_sqdist, apply_scan
+from .scan import quantize_ranges, beam_offsets, scan_sqdist, apply_scan, scan_sqdist_continuous, apply_scan_continuous
 from .difficulty import best_match, difficulty
 from .sample import dither_intensity, floyd_steinberg, floyd_steinberg_c, sample_mask, apply_scan_sampled
 
@@ -61,6 +61,8 @@ __all__ = [
     "beam_offsets",
     "scan_sqdist",
     "apply_scan",
+    "scan_sqdist_continuous",
+    "apply_scan_continuous",
     "dither_intensity",
     "floyd_steinberg",
     "floyd_steinberg_c",

@@ -89,3 +89,44 @@ def apply_scan(state: FilterState, Rq: np.ndarray, zq: np.ndarray, sigma_m: floa
     ns.B = Bp / total
     ns.log_norm = state.log_norm + mstar + math.log(total)
     return ns
+
+
+def scan_sqdist_continuous(R: np.ndarray, z: np.ndarray, s: np.ndarray, chunk: int = 4096) -> np.ndarray:
+    """sum_b (z[b] - R[c, (b + s_k) mod N])^2 in FP64 metres^2, on unquantised ranges: (len(s), n_cells)."""
+    R = np.asarray(R, dtype=np.float64)
+    z = np.asarray(z, dtype=np.float64)
+    n = R.shape[1]
+    out = np.empty((len(s), R.shape[0]), np.float64)
+    b = np.arange(n)
+    for k, sk in enumerate(s):
+        cols = (b + int(sk)) % n
+        for a in range(0, R.shape[0], chunk):
+            diff = z[None, :] - R[a:a + chunk][:, cols]
+            out[k, a:a + chunk] = (diff * diff).sum(axis=1)
+    return out
+
+
+def apply_scan_continuous(state: FilterState, R: np.ndarray, z: np.ndarray, sigma_m: float) -> FilterState:
+    """The per-beam Gaussian of the scan model on unquantised FP64 ranges:
+    L = ln B - sum_b (z_b - r)^2 / (2 sigma^2), then as apply_scan.
+
+    This is the model before the quantisation reading (ranges in multiples of
+    max_range / 256); it measures what that reading costs the posterior and is
+    not the parity reference of the quantised kernels.  With ranges that are
+    already multiples of h it equals apply_scan.
+    """
+    n_theta, H, W = state.B.shape
+    s = beam_offsets(state.theta, n_theta, R.shape[1])
+    D = scan_sqdist_continuous(R, z, s).reshape(n_theta, H, W)
+    ns = state.copy()
+    with np.errstate(divide="ignore"):
+        L = np.log(state.B) - D / (2.0 * sigma_m * sigma_m)
+    mstar = float(L.max())
+    if not math.isfinite(mstar):
+        ns.degenerate = True
+        return ns
+    Bp = np.exp(L - mstar)
+    total = float(Bp.sum())
+    ns.B = Bp / total
+    ns.log_norm = state.log_norm + mstar + math.log(total)
+    return ns

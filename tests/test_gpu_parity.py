@@ -40,6 +40,8 @@ def _run_pair(occ, cell, n_theta, sxy, sth, odo, *, rxy=-1, rth=-1, flags=3, che
             assert th == pytest.approx(st.theta, abs=1e-12)
             assert ln == pytest.approx(st.log_norm, abs=1e-5 + 1e-6 * abs(st.log_norm))
             assert abs(float(b.sum(dtype=np.float64)) - 1.0) < 1e-5
+            if check_every > 1:
+                say(f"[parity] {tag} step {t}: peak-normalised error {err:.3e}")
     say(f"[parity] {tag} worst peak-normalised error {worst:.3e}")
     return f, st
 

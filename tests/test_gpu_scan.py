@@ -103,6 +103,9 @@ def test_distance_is_exact_full_size_sampled():
     assert np.array_equal(d_gpu[:, cells].astype(np.int64), d_ref)
 
 
+_last_prior, _last_scan = [None], [None]  # the prior and scan of the latest step of _motion_and_scans
+
+
 def _motion_and_scans(f32_ops, sigma_scan, seed_pose):
     """30 odometry steps on a 64 x 56 plan with a 90-beam scan every 10 steps;
     yields (t, GPU filter, oracle state, prior oracle state from the GPU's own
@@ -126,6 +129,7 @@ def _motion_and_scans(f32_ops, sigma_scan, seed_pose):
                            seed=t)
             _, _, th, ln_prior = f.read_belief(want_belief=False)
             prior_gpu = oracle_state_from(stored_belief(f), ln_prior, th)
+            _last_prior[0], _last_scan[0] = prior_gpu, z
             zq = O.quantize_ranges(z, 4.0)
             f.apply_scan(z, sigma_scan)
             st = O.apply_scan(st, Rq, zq, sigma_scan, 4.0)
@@ -164,6 +168,27 @@ def test_sharp_scan_log_normaliser_from_the_gpu_prior(f32_ops):
         assert abs(ln - from_prior.log_norm) <= LN_ABS + LN_REL * abs(from_prior.log_norm)
         assert peak_err(b, from_prior.B) <= SCAN_PEAK_TOL
         assert in_tie_set(pose.as_tuple(), from_prior.B, 1e-5)
+
+
+@pytest.mark.parametrize("sigma", [0.1, 0.3, 1.5])
+def test_scan_posterior_against_the_continuous_range_model(sigma):
+    # What the quantisation of ranges to h = max_range / 256 costs: the GPU
+    # posterior (quantised model) against the oracle's per-beam Gaussian on
+    # unquantised FP64 ranges, from the same FP32 prior.  Stated tolerance:
+    # the same most probable state, and L1 <= 0.1 (the oracle's own quantised
+    # and continuous posteriors differ by at most 0.045 on these scans).
+    occ = bsp_rooms(64, 56, seed=34)
+    R = range_table(occ, 0.1, 90, 4.0)
+    for t, f, st, from_prior in _motion_and_scans(False, sigma, 36):
+        b, pose, th, _ = f.read_belief()
+        prior = _last_prior[0]
+        cont = O.apply_scan_continuous(prior, R, _last_scan[0], sigma)
+        l1 = float(np.abs(b.astype(np.float64) - cont.B).sum())
+        best = np.unravel_index(int(np.argmax(cont.B)), cont.B.shape)
+        say(f"[scan] step {t} sigma {sigma}: L1 to the continuous model {l1:.3e}, argmax {pose.as_tuple()} vs "
+            f"{tuple(int(v) for v in best)}")
+        assert l1 <= 0.1
+        assert pose.as_tuple() == tuple(int(v) for v in best)
 
 
 def test_noise_free_scan_peaks_at_the_true_state():

@@ -134,3 +134,37 @@ def test_linear_domain_brute_force_and_log_normaliser():
     assert np.abs(post.B - expect).max() <= 1e-12 * expect.max()
     assert post.log_norm - st.log_norm == pytest.approx(math.log(math.fsum(joint.reshape(-1))),
                                                          abs=1e-12)
+
+
+def test_continuous_model_equals_the_quantised_one_on_quantised_ranges():
+    # with every range a multiple of h, the continuous per-beam Gaussian is the
+    # quantised model: D_continuous = h^2 D_quantised, so the posteriors agree
+    occ = bsp_rooms(30, 26, seed=81)
+    R = range_table(occ, 0.1, 48, 3.0)
+    h = 3.0 / 256
+    Rq = O.quantize_ranges(R, 3.0)
+    Rh = (Rq + 128) * h                         # ranges rounded to multiples of h
+    rng = np.random.default_rng(82)
+    z = rng.uniform(0.0, 3.1, 48)
+    zq = O.quantize_ranges(z, 3.0)
+    zh = (zq + 128) * h
+    st = O.init_uniform(occ, 6)
+    st.theta = 0.4
+    a = O.apply_scan(st, Rq, zq, 0.2, 3.0)
+    b = O.apply_scan_continuous(st, Rh, zh, 0.2)
+    assert np.allclose(a.B, b.B, rtol=0, atol=1e-12 * a.B.max())
+    assert abs(a.log_norm - b.log_norm) < 1e-9
+    # and the direct distance is h^2 times the integer one
+    s = O.beam_offsets(0.4, 6, 48)
+    assert np.allclose(O.scan_sqdist_continuous(Rh, zh, s), h * h * O.scan_sqdist(Rq, zq, s), rtol=1e-12, atol=0)
+
+
+def test_continuous_distance_brute_force():
+    # one cell, two channels, four beams written out by hand
+    R = np.array([[1.0, 2.0, 3.0, 4.0]])
+    z = np.array([1.5, 2.0, 2.0, 5.0])
+    s = np.array([0, 1])
+    # k = 0: columns 0, 1, 2, 3; k = 1: columns 1, 2, 3, 0
+    d0 = 0.25 + 0.0 + 1.0 + 1.0
+    d1 = (1.5 - 2.0) ** 2 + (2.0 - 3.0) ** 2 + (2.0 - 4.0) ** 2 + (5.0 - 1.0) ** 2
+    assert np.allclose(O.scan_sqdist_continuous(R, z, s)[:, 0], [d0, d1], rtol=0, atol=1e-15)
