@@ -155,7 +155,8 @@ size_t mcl_filter_workspace_bytes(mcl_map map, const mcl_params* params);
  * init_host == NULL: B_0 uniform over the free cells of every heading channel.
  * Otherwise init_host is a host FP32 array of n_theta*H*W non-negative values
  * (any scale; it is renormalised) that becomes B_0 (checkpoint resume); it is
- * stored divided by its largest value, as the steps store the belief, so a
+ * stored multiplied by the power of two that brings its largest value into
+ * [1/2, 1) (exact), as the steps store the belief near a peak of one, so a
  * sum-one export resumes in 16-bit storage without flushing small values.
  * theta0_rad sets the running heading offset.  sigma_xy / radius_xy / flags
  * must equal those the map was built with.  With init_host the call returns

@@ -496,14 +496,18 @@ mcl_status mcl_init_belief(mcl_map map, const mcl_params* p, void* ws, size_t ws
       e = launch_dev_init(f->dev, static_cast<double>(map->n_free) * f->T, 1.0f, f->stream);
   } else {
     const size_t eb = dtype_bytes(f->dtype);
-    const double inv = 1.0 / static_cast<double>(init_max);
-    const float init_scale = inv > static_cast<double>(FLT_MAX) ? FLT_MAX : static_cast<float>(inv);
+    // a power of two that brings the largest value into [1/2, 1): exact in
+    // every storage type (no rounding beyond the type's own)
+    int ex = 0;
+    (void)frexp(static_cast<double>(init_max), &ex);
+    const float init_scale = static_cast<float>(ldexp(1.0, std::min(127, -ex)));
     e = hipMemsetAsync(f->buf[1], 0, static_cast<size_t>(f->sstride) * f->T * eb, f->stream);
     for (int k = 0; k < f->T && e == hipSuccess; ++k) {
       e = hipMemcpyAsync(f->staging, init_host + k * plane, plane * sizeof(float), hipMemcpyHostToDevice,
                          f->stream);
-      // stored max-scaled (peak one), as every step stores it: a sum-one
-      // belief of many states lies below the 16-bit types' smallest values
+      // stored scaled to a peak in [1/2, 1), as every step stores it near
+      // one: a sum-one belief of many states lies below the 16-bit types'
+      // smallest values
       if (e == hipSuccess)
         e = launch_slice_from_f32(f->dtype, f->staging, static_cast<char*>(f->buf[0]) + k * f->sstride * eb,
                                   map->W, map->H, map->pitch, init_scale, f->stream);
@@ -1048,21 +1052,24 @@ static mcl_status check_batch(mcl_filter* const filters, const double* uvw, int3
   return MCL_OK;
 }
 
+// One filter's launch in a batch.
+struct BatchJob {
+  StepArgs a;
+  int dtype, radius;
+  KernelShape k;
+  mcl_filter f;
+};
+
 // Host side of one batched step: each filter's bookkeeping as in
 // mcl_step_odometry (a filter whose sub-cell gate does not fire takes no
 // launch; anisotropic filters launch their own passes on s), then the job
 // table, offsets and shift tables written into `host` (laid out as
-// slot_layout(n)) with device pointers into `dev`.  *used = bytes to copy.
+// slot_layout(n)) with device pointers into `dev`.  jobs and groups are
+// caller storage for n entries each (nothing is allocated here); *ngroups =
+// launch groups, *used = bytes to copy.
 static mcl_status plan_batch(mcl_filter* const filters, const double* uvw, int32_t n, hipStream_t s, char* host,
-                             char* dev, std::vector<BatchGroup>& groups, size_t* used) {
-  struct Job {
-    StepArgs a;
-    int dtype, radius;
-    KernelShape k;
-    mcl_filter f;
-  };
-  std::vector<Job> jobs;
-  jobs.reserve(n);
+                             char* dev, BatchJob* jobs, BatchGroup* groups, int* ngroups, size_t* used) {
+  int njobs = 0;
   for (int i = 0; i < n; ++i) {
     mcl_filter f = filters[i];
     const double u = uvw[3 * i], v = uvw[3 * i + 1], w = uvw[3 * i + 2];
@@ -1076,30 +1083,41 @@ static mcl_status plan_batch(mcl_filter* const filters, const double* uvw, int32
       HIP_TRY(launch_aniso_step(f->dtype, make_aniso_args(f, a, theta_pre), s), "step launch");
       continue;
     }
-    jobs.push_back(Job{a, f->dtype, f->radius, f->shape.k, f});
+    jobs[njobs++] = BatchJob{a, f->dtype, f->radius, f->shape.k, f};
   }
-  groups.clear();
+  *ngroups = 0;
   *used = 0;
-  if (jobs.empty()) return MCL_OK;
-  auto same = [](const Job& x, const Job& y) { return x.dtype == y.dtype && x.radius == y.radius && x.k == y.k; };
-  auto less = [](const Job& x, const Job& y) {
+  if (njobs == 0) return MCL_OK;
+  auto same = [](const BatchJob& x, const BatchJob& y) {
+    return x.dtype == y.dtype && x.radius == y.radius && x.k == y.k;
+  };
+  auto less = [](const BatchJob& x, const BatchJob& y) {
     if (x.dtype != y.dtype) return x.dtype < y.dtype;
     if (x.radius != y.radius) return x.radius < y.radius;
     return x.k < y.k;
   };
-  std::stable_sort(jobs.begin(), jobs.end(), less);
+  // stable insertion sort by kernel group (no temporary buffer)
+  for (int i = 1; i < njobs; ++i) {
+    const BatchJob x = jobs[i];
+    int j = i;
+    while (j > 0 && less(x, jobs[j - 1])) {
+      jobs[j] = jobs[j - 1];
+      --j;
+    }
+    jobs[j] = x;
+  }
   const SlotLayout lay = slot_layout(n);
   StepArgs* args = reinterpret_cast<StepArgs*>(host + lay.args_off);
   int32_t* first = reinterpret_cast<int32_t*>(host + lay.first_off);
   ShiftEntry* tables = reinterpret_cast<ShiftEntry*>(host + lay.tables_off);
   const ShiftEntry* tables_dev = reinterpret_cast<const ShiftEntry*>(dev + lay.tables_off);
-  int nfirst = 0, ntab = 0;
-  for (size_t i = 0; i < jobs.size(); ++i) {
+  int nfirst = 0, ntab = 0, ng = 0;
+  for (int i = 0; i < njobs; ++i) {
     if (i == 0 || !same(jobs[i], jobs[i - 1])) {
-      if (!groups.empty()) first[nfirst++] = groups.back().blocks;
-      groups.push_back(BatchGroup{jobs[i].dtype, jobs[i].radius, jobs[i].k, static_cast<int>(i), nfirst, 0, 0, 0});
+      if (ng > 0) first[nfirst++] = groups[ng - 1].blocks;
+      groups[ng++] = BatchGroup{jobs[i].dtype, jobs[i].radius, jobs[i].k, i, nfirst, 0, 0, 0};
     }
-    BatchGroup& g = groups.back();
+    BatchGroup& g = groups[ng - 1];
     first[nfirst++] = g.blocks;
     args[i] = jobs[i].a;
     if (jobs[i].k.variant != 0) {
@@ -1112,16 +1130,18 @@ static mcl_status plan_batch(mcl_filter* const filters, const double* uvw, int32
     g.max_theta = std::max(g.max_theta, static_cast<int>(jobs[i].a.n_theta));
     ++g.njobs;
   }
-  first[nfirst++] = groups.back().blocks;
+  first[nfirst++] = groups[ng - 1].blocks;
+  *ngroups = ng;
   *used = lay.tables_off + static_cast<size_t>(ntab) * sizeof(ShiftEntry);
   return MCL_OK;
 }
 
-static hipError_t launch_groups(const std::vector<BatchGroup>& groups, char* dev, int32_t n, hipStream_t s) {
+static hipError_t launch_groups(const BatchGroup* groups, int ngroups, char* dev, int32_t n, hipStream_t s) {
   const SlotLayout lay = slot_layout(n);
   const StepArgs* args_dev = reinterpret_cast<const StepArgs*>(dev + lay.args_off);
   const int32_t* first_dev = reinterpret_cast<const int32_t*>(dev + lay.first_off);
-  for (const BatchGroup& g : groups) {
+  for (int i = 0; i < ngroups; ++i) {
+    const BatchGroup& g = groups[i];
     const hipError_t e = launch_step_batch(g.dtype, g.radius, g.k, args_dev + g.job0, first_dev + g.first0, g.njobs,
                                            g.blocks, g.max_theta, s);
     if (e != hipSuccess) return e;
@@ -1143,14 +1163,17 @@ mcl_status mcl_step_batch(mcl_filter* const filters, const double* uvw, int32_t 
   if (ws_bytes < lay.bytes) return fail(MCL_ENOMEM, "batch workspace needs %zu bytes", lay.bytes);
   hipStream_t s = static_cast<hipStream_t>(stream);
   std::vector<char> host(lay.bytes);
-  std::vector<BatchGroup> groups;
+  std::vector<BatchJob> jobs(n);
+  std::vector<BatchGroup> groups(n);
+  int ngroups = 0;
   size_t used = 0;
   char* dev = static_cast<char*>(dev_ws);
-  if ((st = plan_batch(filters, uvw, n, s, host.data(), dev, groups, &used)) != MCL_OK) return st;
-  if (groups.empty()) return MCL_OK;
+  if ((st = plan_batch(filters, uvw, n, s, host.data(), dev, jobs.data(), groups.data(), &ngroups, &used)) != MCL_OK)
+    return st;
+  if (ngroups == 0) return MCL_OK;
   // a copy from pageable memory: the host buffer may be released on return
   HIP_TRY(hipMemcpyAsync(dev, host.data(), used, hipMemcpyHostToDevice, s), "batch jobs upload");
-  HIP_TRY(launch_groups(groups, dev, n, s), "batch launch");
+  HIP_TRY(launch_groups(groups.data(), ngroups, dev, n, s), "batch launch");
   return MCL_OK;
 }
 
@@ -1228,10 +1251,15 @@ mcl_status mcl_batch_step(mcl_batch b, mcl_filter* const filters, const double* 
   // the slot's previous replay must have read its parameters
   if (b->pending[slot]) HIP_TRY(hipEventSynchronize(b->done[slot]), "batch slot wait");
   b->pending[slot] = false;
-  std::vector<BatchGroup> groups;
+  std::vector<BatchJob> jobs(n);
+  std::vector<BatchGroup> groups(n);
+  int ngroups = 0;
   size_t used = 0;
-  if ((st = plan_batch(filters, uvw, n, b->stream, b->host[slot], b->dev[slot], groups, &used)) != MCL_OK) return st;
-  if (groups.empty()) return MCL_OK;
+  if ((st = plan_batch(filters, uvw, n, b->stream, b->host[slot], b->dev[slot], jobs.data(), groups.data(), &ngroups,
+                       &used)) != MCL_OK)
+    return st;
+  if (ngroups == 0) return MCL_OK;
+  groups.resize(ngroups);
   b->next ^= 1;
   // the graph depends on the launch structure and the copied size, not on the
   // parameters, which the copy node reads from the pinned slot at every replay
@@ -1249,7 +1277,7 @@ mcl_status mcl_batch_step(mcl_batch b, mcl_filter* const filters, const double* 
     hipGraph_t graph = nullptr;
     HIP_TRY(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal), "graph capture");
     hipError_t e = hipMemcpyAsync(b->dev[slot], b->host[slot], used, hipMemcpyHostToDevice, b->stream);
-    if (e == hipSuccess) e = launch_groups(groups, b->dev[slot], n, b->stream);
+    if (e == hipSuccess) e = launch_groups(groups.data(), ngroups, b->dev[slot], n, b->stream);
     const hipError_t e2 = hipStreamEndCapture(b->stream, &graph);
     if (e == hipSuccess) e = e2;
     if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
