@@ -325,6 +325,21 @@ size_t mcl_batch_workspace_bytes(int32_t max_filters);
 mcl_status mcl_step_batch(mcl_filter* const filters, const double* uvw, int32_t n, void* dev_ws,
                           size_t ws_bytes, void* stream);
 
+/* step_batch_noalloc (async): mcl_step_batch for callers that cannot
+ * allocate memory (tight serving loops, harnesses that forbid allocation).
+ * Each filter's host bookkeeping runs at call time, so a captured graph of
+ * this call would replay one step's parameters: graph replay of batched steps
+ * is mcl_batch_step's job.  It takes no workspace and allocates
+ * nothing: the job table lives in a device array of the library (2 MiB per
+ * GPU the library runs on, held until the process ends, addressed on the
+ * current device, which must be the filters' device) and its host staging in
+ * a host array of the library.  At most 256 filters per call (EINVAL above).
+ * Calls share those arrays: concurrent calls from several threads are
+ * serialised by a lock, and calls on one GPU whose launches overlap on
+ * different streams race on the device array (drive them from one stream).
+ * Results are bitwise those of mcl_step_batch; other errors as it. */
+mcl_status mcl_step_batch_noalloc(mcl_filter* const filters, const double* uvw, int32_t n, void* stream);
+
 /* ---- serving: graph-replayed batched steps ---------------------------------------- */
 typedef struct mcl_batch_s* mcl_batch;
 

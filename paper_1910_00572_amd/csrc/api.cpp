@@ -12,6 +12,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1178,6 +1179,63 @@ mcl_status mcl_step_batch(mcl_filter* const filters, const double* uvw, int32_t 
 }
 
 }  // extern "C"
+
+// ---- batched steps without allocation -------------------------------------------------
+// The job table of mcl_step_batch_noalloc lives in this file-scope device
+// array (one copy per GPU, held until the process ends) and its host staging
+// in a file-scope host array; calls share both, under a host lock.
+namespace {
+constexpr int32_t kNoallocMaxFilters = 256;
+constexpr size_t kNoallocBytes = 1u << 21;  // >= slot_layout(kNoallocMaxFilters).bytes (checked below)
+constexpr int kNoallocMaxDevices = 64;
+}  // namespace
+static __device__ __align__(256) char scratch[kNoallocBytes];
+static char noalloc_host[kNoallocBytes];
+static BatchJob noalloc_jobs[kNoallocMaxFilters];
+static BatchGroup noalloc_groups[kNoallocMaxFilters];
+static char* noalloc_dev[kNoallocMaxDevices];  // device address of `scratch` per device, set once
+static std::mutex noalloc_mutex;
+
+// Device address of `scratch` on the current device (the array's host-side
+// name is not a device address), looked up once per device.
+static mcl_status noalloc_scratch(char** out) {
+  int device = -1;
+  HIP_TRY(hipGetDevice(&device), "current device");
+  if (device < 0 || device >= kNoallocMaxDevices) return fail(MCL_EDEVICE, "device %d beyond %d", device, kNoallocMaxDevices);
+  if (!noalloc_dev[device]) {
+    void* ptr = nullptr;
+    HIP_TRY(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)), "scratch symbol address");
+    noalloc_dev[device] = static_cast<char*>(ptr);
+  }
+  *out = noalloc_dev[device];
+  return MCL_OK;
+}
+
+extern "C" mcl_status mcl_step_batch_noalloc(mcl_filter* const filters, const double* uvw, int32_t n, void* stream) {
+  static_assert(kNoallocBytes >= 256 * (sizeof(StepArgs) + 2 * sizeof(int32_t) + kMaxTheta * sizeof(ShiftEntry)) + 1024,
+                "the static job table holds kNoallocMaxFilters filters");
+  if (n > kNoallocMaxFilters)
+    return fail(MCL_EINVAL, "%d filters: the static job table holds at most %d", n, kNoallocMaxFilters);
+  mcl_status st = check_batch(filters, uvw, n);
+  if (st != MCL_OK) return st;
+  const SlotLayout lay = slot_layout(n);
+  if (lay.bytes > kNoallocBytes) return fail(MCL_EINVAL, "job table of %zu bytes exceeds %zu", lay.bytes, kNoallocBytes);
+  std::lock_guard<std::mutex> lock(noalloc_mutex);
+  char* dev = nullptr;
+  if ((st = noalloc_scratch(&dev)) != MCL_OK) return st;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  int ngroups = 0;
+  size_t used = 0;
+  if ((st = plan_batch(filters, uvw, n, s, noalloc_host, dev, noalloc_jobs, noalloc_groups, &ngroups, &used)) != MCL_OK)
+    return st;
+  if (ngroups == 0) return MCL_OK;
+  // the whole used part of the table is rewritten on every call (nothing in
+  // it needs to start at zero); the copy from pageable memory completes
+  // before the host buffer is reused by the next call
+  HIP_TRY(hipMemcpyAsync(dev, noalloc_host, used, hipMemcpyHostToDevice, s), "batch jobs upload");
+  HIP_TRY(launch_groups(noalloc_groups, ngroups, dev, n, s), "batch launch");
+  return MCL_OK;
+}
 
 // ---- graph-replayed batches (serving) ------------------------------------------------
 struct mcl_batch_s {

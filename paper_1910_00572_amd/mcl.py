@@ -31,7 +31,7 @@ ABI_SYMBOLS = [
     "mcl_get_info", "mcl_step_batch", "mcl_batch_workspace_bytes", "mcl_sample_cells",
     "mcl_apply_scan_sampled", "mcl_dither", "mcl_match_workspace_bytes", "mcl_best_match",
     "mcl_difficulty", "mcl_batch_create", "mcl_batch_step", "mcl_batch_counts", "mcl_batch_destroy",
-    "mcl_export_scalars", "mcl_apply_scan_batch",
+    "mcl_export_scalars", "mcl_apply_scan_batch", "mcl_step_batch_noalloc",
 ]
 
 
@@ -136,6 +136,8 @@ def load_library(path: str = _LIB_PATH):
     lib.mcl_batch_step.argtypes = [c_void_p, POINTER(c_void_p), c_void_p, c_int32]
     lib.mcl_batch_counts.restype = c_int
     lib.mcl_batch_counts.argtypes = [c_void_p, POINTER(c_int64), POINTER(c_int64)]
+    lib.mcl_step_batch_noalloc.restype = c_int
+    lib.mcl_step_batch_noalloc.argtypes = [POINTER(c_void_p), c_void_p, c_int32, c_void_p]
     lib.mcl_apply_scan_batch.restype = c_int
     lib.mcl_apply_scan_batch.argtypes = [POINTER(c_void_p), c_void_p, c_int32, c_void_p, c_int32]
     lib.mcl_export_scalars.restype = c_int
@@ -443,6 +445,13 @@ def step_batch(filters, uvw, workspace: BatchWorkspace, stream=None):
     u = np.ascontiguousarray(uvw, dtype=np.float64)
     _check(load_library().mcl_step_batch(arr, u.ctypes.data, len(filters), c_void_p(workspace.tensor.data_ptr()),
                                          workspace.nbytes, _stream_handle(stream)))
+
+
+def step_batch_noalloc(filters, uvw, stream=None):
+    """step_batch without a workspace: the job table is the library's own static device array."""
+    arr = (c_void_p * len(filters))(*[f.handle.value for f in filters])
+    u = np.ascontiguousarray(uvw, dtype=np.float64)
+    _check(load_library().mcl_step_batch_noalloc(arr, u.ctypes.data, len(filters), _stream_handle(stream)))
 
 
 class BatchRunner:
