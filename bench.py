@@ -99,7 +99,7 @@ def _cpu_model():
     return "unknown"
 
 
-def _oracle_worker(args):
+def _oracle_worker(args, progress=False):
     """One oracle filter on the headline workload: (states*steps, seconds) of `steps` timed steps."""
     import os as _os
     _os.environ.setdefault("OMP_NUM_THREADS", "1")
@@ -114,6 +114,8 @@ def _oracle_worker(args):
     t0 = time.perf_counter()
     for t in range(steps):
         st = O.step(st, occ, p, *odo[t], M=M)
+        if progress:
+            log(f"[bench] oracle {size}x{size}x{n_theta}: step {t + 1}/{steps}, {time.perf_counter() - t0:.1f} s")
     return occ.size * n_theta * steps, time.perf_counter() - t0
 
 
@@ -150,7 +152,7 @@ def cpu_baseline(occ, odo, n_theta, sigma, steps=8, pool_steps=3):
 
 def cpu_baseline_large(steps=5):
     """The FP64 oracle on the 1024x1024x128 workload (one filter, one core), `steps` steps."""
-    n, dt = _oracle_worker((1024, 128, 1.0, steps, 5))
+    n, dt = _oracle_worker((1024, 128, 1.0, steps, 5), progress=True)
     return {"value": n / dt, "unit": "states*steps/s", "cores": 1, "kind": "oracle",
             "sample": f"{steps} steps of the 1024x1024x128 FP64 oracle (numpy, one core), {dt:.1f} s",
             "cpu_model": _cpu_model()}
@@ -296,7 +298,8 @@ def bench_sampled(n_scans, n_samples=4096):
     torch.cuda.synchronize()
     sel_ms = float(np.mean([a.elapsed_time(b) for a, b, _ in ev]))
     upd_ms = float(np.mean([b.elapsed_time(c) for _, b, c in ev]))
-    phases = (511 + 4 * 511) // 3 + 1  # wavefront phases of three steps on a 512 x 512 map
+    # one-wave dithering of a 512 x 512 map: eight cells per phase, cell (i, j) at step i + 9 j
+    phases = (511 + 9 * 511) // 8 + 1
     # steps with a sampled scan every 10 steps, 100 steps
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -311,7 +314,7 @@ def bench_sampled(n_scans, n_samples=4096):
     out = {"n_samples_requested": n_samples, "cells_selected": counts[0],
            "select_ms": sel_ms, "update_ms": upd_ms,
            "select_plus_update_ms": sel_ms + upd_ms,
-           "dither_phases": phases,
+           "dither_phases": phases, "dither_kernel": "one wave, eight cells per phase",
            "belief_read_bytes_select": states * 4, "belief_read_bytes_update": states * 4,
            "steps_with_sampled_scan_every_10_states_steps_per_s": states * 100 / dt}
     del f, m

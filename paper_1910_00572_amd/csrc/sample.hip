@@ -164,6 +164,103 @@ __global__ __launch_bounds__(kDitherMaxThreads) void dither_kernel(DitherArgs a)
   }
 }
 
+// One-wave variant: no LDS and no barrier.  Lane l takes rows l, l + 64,
+// l + 128, ... in turn, K cells per phase, cell (i, j) at step i + (K+1) j as
+// above.  The row below needs, in its next phase, this row's errors at its
+// columns i0-1 .. i0+K: the last two cells of this lane's phase before last
+// and the K cells of its last phase.  Each lane keeps those K + 2 values and
+// the lane below reads them by a one-lane rotation of the wave (lane 0, which
+// holds row 64 m, reads lane 63, which holds row 64 m - 1).  Cells outside the
+// image (columns < 0 or >= W, rows >= H) carry error zero, so the rows above
+// row 0 and the borders need no tests.  A lane moves to its next row once that
+// row's first step falls in the phase; with 63 (K+1) >= W + 2K + 2 the row
+// below has by then stopped reading the old row, and the lane above moved on
+// only after this lane's row stopped reading it.  The arithmetic and its order
+// are those of dither_kernel.
+template <int K, int PF>
+__global__ __launch_bounds__(64) void dither_wave_kernel(DitherArgs a) {
+#pragma clang fp contract(off)
+  const int l = threadIdx.x;
+  const int W = a.W, H = a.H;
+  const float w7 = 7.f / 16.f, w3 = 3.f / 16.f, w5 = 5.f / 16.f, w1 = 1.f / 16.f;
+  const __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<float*>(a.src), static_cast<short>(0), static_cast<int>(a.cells * 4u), 0x00020000);
+  const __amdgpu_buffer_rsrc_t rmask_out = __builtin_amdgcn_make_buffer_rsrc(
+      a.mask, static_cast<short>(0), static_cast<int>(a.cells), 0x00020000);
+  constexpr uint32_t kOut = 0x80000000u;  // at or past the end of both buffers
+  constexpr int kRowStep = 64 * (K + 1);  // steps between two rows of one lane
+
+  int j = l, jf = l;            // row of this phase; row of the phase being prefetched
+  int next = kRowStep + (K + 1) * l, nextf = next;  // first step of the lane's next row
+  float hist[K + 2], elast[K];
+#pragma unroll
+  for (int c = 0; c < K + 2; ++c) hist[c] = 0.f;
+#pragma unroll
+  for (int c = 0; c < K; ++c) elast[c] = 0.f;
+  float eleft = 0.f;
+  float pf[PF][K];
+  // Intensities of phase q: every cell of the phase with a column >= 0 has a
+  // non-negative offset (W >= K), so one out-of-range marker per phase covers
+  // phases without such a cell; a cell outside the image reads a value it
+  // never uses.
+  auto load_phase = [&](int q, float (&dst)[K]) {
+    if (q * K + K - 1 >= nextf) {
+      jf += 64;
+      nextf += kRowStep;
+    }
+    const int base = jf * W + (q * K - (K + 1) * jf);
+    const uint32_t off = base >= 0 ? static_cast<uint32_t>(base) * 4u : kOut;
+#pragma unroll
+    for (int c = 0; c < K; ++c)
+      dst[c] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rsrc, off + 4u * c, 0, 0));
+  };
+#pragma unroll
+  for (int u = 0; u < PF; ++u) load_phase(u, pf[u]);
+
+  for (int p0 = 0; p0 < a.phases; p0 += PF) {
+#pragma unroll
+    for (int u = 0; u < PF; ++u) {
+      const int p = p0 + u;
+      if (p * K + K - 1 >= next) {
+        j += 64;
+        next += kRowStep;
+      }
+      // columns i0-1 .. i0+K of the row above, from the lane above
+      float ua[K + 2];
+#pragma unroll
+      for (int c = 0; c < K + 2; ++c)  // wave_ror:1, every lane has a source
+        ua[c] = __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, hist[c]), 0x13C, 0xf, 0xf,
+                                                                   true));
+      const int i0 = p * K - (K + 1) * j;
+      // a row past the last reads as a column past the end
+      const uint32_t wlim = j < H ? static_cast<uint32_t>(W) : 0u;
+      const uint32_t rb = static_cast<uint32_t>(j) * static_cast<uint32_t>(W);
+      float ecur[K];
+#pragma unroll
+      for (int c = 0; c < K; ++c) {
+        const int i = i0 + c;
+        const bool act = static_cast<uint32_t>(i) < wlim;
+        const float err = ((w1 * ua[c] + w5 * ua[c + 1]) + w3 * ua[c + 2]) + w7 * eleft;
+        const float v = pf[u][c] + err;
+        const bool sel = v >= 0.5f;
+        const float e = act ? v - (sel ? 1.f : 0.f) : 0.f;
+        eleft = e;
+        ecur[c] = e;
+        __builtin_amdgcn_raw_buffer_store_b8(static_cast<uint8_t>(sel ? 1 : 0), rmask_out,
+                                             act ? rb + static_cast<uint32_t>(i) : kOut, 0, 0);
+      }
+      hist[0] = elast[K - 2];
+      hist[1] = elast[K - 1];
+#pragma unroll
+      for (int c = 0; c < K; ++c) {
+        hist[c + 2] = ecur[c];
+        elast[c] = ecur[c];
+      }
+      load_phase(p + PF, pf[u]);
+    }
+  }
+}
+
 // I = min(1, n m / total) in place (FP32 product and quotient rounded to
 // nearest; a total that is not positive gives I = 0).
 __global__ void intensity_kernel(float* __restrict__ m, uint32_t cells, float n, const FilterDev* __restrict__ dev) {
@@ -320,6 +417,25 @@ DitherPlan choose_plan(int W, int H) {
   return p;
 }
 
+// Cells per phase of the one-wave kernel for width W: the smallest of 8, 16
+// and 32 with 63 (K+1) >= W + 2K + 2 (and K <= W); 0 if none.
+int wave_k(int W) {
+  for (int K : {8, 16, 32})
+    if (K <= W && 63 * (K + 1) >= W + 2 * K + 2) return K;
+  return 0;
+}
+
+template <int K>
+hipError_t launch_wave(const DitherArgs& a0, hipStream_t s) {
+  constexpr int PF = 128 / K;  // loads in flight about PF phases ahead
+  DitherArgs a = a0;
+  const int64_t last = static_cast<int64_t>(a.W) - 1 + static_cast<int64_t>(K + 1) * (a.H - 1);
+  const int64_t phases = last / K + 1;
+  a.phases = static_cast<int32_t>((phases + PF - 1) / PF * PF);
+  hipLaunchKernelGGL((dither_wave_kernel<K, PF>), dim3(1), dim3(64), 0, s, a);
+  return hipGetLastError();
+}
+
 template <int K, int MAXA>
 hipError_t launch_k(const DitherArgs& a0, const DitherPlan& p, hipStream_t s) {
   constexpr int PF = K == 1 ? 16 : 4;
@@ -359,6 +475,12 @@ hipError_t launch_dither(const float* src, int W, int H, uint8_t* mask, bool sca
     hipLaunchKernelGGL(intensity_kernel, dim3(blocks), dim3(256), 0, s, const_cast<float*>(src), a.cells, n_samples, dev);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+  }
+  switch (wave_k(W)) {
+    case 8: return launch_wave<8>(a, s);
+    case 16: return launch_wave<16>(a, s);
+    case 32: return launch_wave<32>(a, s);
+    default: break;
   }
   if (p.K == 3) {
     if (p.slots == 1) return launch_k<3, 1>(a, p, s);

@@ -92,6 +92,17 @@ def test_dither_is_bit_exact_large(shape):
     assert np.array_equal(_gpu_dither(img), O.floyd_steinberg_c(img))
 
 
+# Widths at the edges of the one-wave kernel's cell counts per phase (8 up to
+# width 549, 16 up to 1037, 32 up to 2013) and just past them; width 7 and
+# width 2014 take the workgroup kernel.
+@pytest.mark.parametrize("shape", [(9, 8), (70, 549), (70, 550), (200, 1000), (150, 1037), (150, 1038),
+                                   (120, 2013), (40, 2014), (30, 7)], ids=lambda s: f"{s[0]}x{s[1]}")
+def test_dither_is_bit_exact_at_phase_width_edges(shape):
+    img = _intensity(shape, "uniform", _seed(shape, "edges"))
+    say(f"[dither] edges {shape}")
+    assert np.array_equal(_gpu_dither(img), O.floyd_steinberg_c(img))
+
+
 def test_dither_sizes_and_errors():
     import torch
     from paper_1910_00572_amd import mcl
