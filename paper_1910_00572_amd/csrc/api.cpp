@@ -608,11 +608,12 @@ static hipError_t plan_motion(mcl_filter f, double u, double v, double w, StepAr
   return hipSuccess;
 }
 
-// Launch the fused step of one filter: variant-1 streaming kernels take the
-// shift table from the kernel arguments (or, above kArgTableMax channels,
-// from the filter's device table, written here through kernel arguments).
+// Launch the fused step of one filter: the streaming kernels take the shift
+// table from the kernel arguments (or, above kArgTableMax channels, from the
+// filter's device table, written here through kernel arguments); the tiled
+// kernel computes its own.
 static hipError_t launch_filter_step(mcl_filter f, StepArgs& a) {
-  if (f->shape.k.variant == 0) return launch_step(f->dtype, f->radius, f->shape.k, a, nullptr, f->stream);
+  if (f->shape.k.tx > 0) return launch_step(f->dtype, f->radius, f->shape.k, a, nullptr, f->stream);
   if (f->T <= kArgTableMax) {
     ShiftArgs tab;
     memcpy(tab.e, f->table, static_cast<size_t>(f->T) * sizeof(ShiftEntry));
@@ -668,7 +669,7 @@ mcl_status mcl_step_odometry(mcl_filter f, double u, double v, double w) {
   bool launch = false;
   const double theta_pre = f->theta;
   const bool aniso = (f->map->flags & MCL_ANISOTROPIC) != 0;
-  HIP_TRY(plan_motion(f, u, v, w, a, f->stream, &launch, aniso || f->shape.k.variant == 0), "shift table");
+  HIP_TRY(plan_motion(f, u, v, w, a, f->stream, &launch, aniso || f->shape.k.tx > 0), "shift table");
   if (!launch) return MCL_OK;
   if (aniso) {
     HIP_TRY(launch_aniso_step(f->dtype, make_aniso_args(f, a, theta_pre), f->stream), "step launch");
@@ -1078,7 +1079,7 @@ static mcl_status plan_batch(mcl_filter* const filters, const double* uvw, int32
     bool launch = false;
     const double theta_pre = f->theta;
     const bool aniso = (f->map->flags & MCL_ANISOTROPIC) != 0;
-    HIP_TRY(plan_motion(f, u, v, w, a, s, &launch, aniso || f->shape.k.variant == 0), "shift table");
+    HIP_TRY(plan_motion(f, u, v, w, a, s, &launch, aniso || f->shape.k.tx > 0), "shift table");
     if (!launch) continue;
     if (aniso) {
       HIP_TRY(launch_aniso_step(f->dtype, make_aniso_args(f, a, theta_pre), s), "step launch");
@@ -1121,8 +1122,8 @@ static mcl_status plan_batch(mcl_filter* const filters, const double* uvw, int32
     BatchGroup& g = groups[ng - 1];
     first[nfirst++] = g.blocks;
     args[i] = jobs[i].a;
-    if (jobs[i].k.variant != 0) {
-      // variant-1/2 kernels read the job's shift table from the slot
+    if (jobs[i].k.tx == 0) {
+      // the streaming kernels read the job's shift table from the slot
       args[i].table = tables_dev + ntab;
       memcpy(tables + ntab, jobs[i].f->table, static_cast<size_t>(jobs[i].f->T) * sizeof(ShiftEntry));
       ntab += jobs[i].f->T;

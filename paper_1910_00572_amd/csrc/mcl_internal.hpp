@@ -98,8 +98,8 @@ struct StepArgs {
   double theta_prev, dtheta;  // heading offset before the step, 2 pi / n_theta
   float gxy[kMaxTaps];        // x/y taps, centred at index R of the kernel radius
   float gth[kMaxTaps];        // theta taps
-  const int32_t* ishift;      // whole-cell shifts (nx, ny) per channel, or null: computed from u, v
-  const ShiftEntry* table;    // streaming kernel: per-channel shift table in device memory, or null
+  const int32_t* ishift;      // tiled kernel: whole-cell shifts (nx, ny) per channel, or null: computed from u, v
+  const ShiftEntry* table;    // streaming kernels: per-channel shift table in device memory, or null
                               // (then the table travels in the kernel arguments)
 };
 

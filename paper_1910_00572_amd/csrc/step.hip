@@ -566,7 +566,8 @@ __device__ inline float from_right(float v) {
 }
 
 template <typename T, int R, int TY, int WAVES, int NBUF>
-__device__ __forceinline__ void stream_body(const StepArgs& a, const int blk, const int nblk) {
+__device__ __forceinline__ void stream_body(const StepArgs& a, const ShiftEntry* __restrict__ tab, const int blk,
+                                            const int nblk) {
   constexpr int NT = 64 * WAVES;
   constexpr int NS = TY + 2 * R;   // S rows
   constexpr int NR = NS + 1;       // source rows
@@ -625,25 +626,14 @@ __device__ __forceinline__ void stream_body(const StepArgs& a, const int blk, co
   const float scale = dev->scale;
   const T* __restrict__ bin = static_cast<const T*>(a.buf[cur]);
   T* __restrict__ bout = static_cast<T*>(a.buf[cur ^ 1]);
-  const double u = a.u_cells, v = a.v_cells, th0 = a.theta_prev, dth = a.dtheta;
-
+  // the host's per-channel shift table (FP64 displacement split into whole
+  // cells and a bilinear fraction), copied to LDS
   for (int k = t; k < nth; k += NT) {
-    if (a.ishift) {
-      pnx[k] = a.ishift[2 * k];
-      pny[k] = a.ishift[2 * k + 1];
-      pfx[k] = 0.f;
-      pfy[k] = 0.f;
-      continue;
-    }
-    double sn, cs;
-    sincos(th0 + k * dth, &sn, &cs);
-    const double dx = u * cs - v * sn;
-    const double dy = u * sn + v * cs;
-    const double fdx = floor(dx), fdy = floor(dy);
-    pnx[k] = static_cast<int>(fdx);
-    pny[k] = static_cast<int>(fdy);
-    pfx[k] = static_cast<float>(dx - fdx);
-    pfy[k] = static_cast<float>(dy - fdy);
+    const ShiftEntry e = tab[k];
+    pnx[k] = e.nx;
+    pny[k] = e.ny;
+    pfx[k] = e.fx;
+    pfy[k] = e.fy;
   }
   float gx[TAPS], gt[TAPS];
 #pragma unroll
@@ -1481,9 +1471,9 @@ constexpr int stream_waves_per_eu() {
 
 template <typename T, int R, int TY, int WAVES, int NBUF>
 __global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(stream_waves_per_eu<WAVES>())))
-void stream_single(StepArgs a) {
+void stream_single(StepArgs a, ShiftArgs tab) {
   const int n = a.tiles_x * a.tiles_y * a.chunks;
-  stream_body<T, R, TY, WAVES, NBUF>(a, xcd_remap(blockIdx.x, n), n);
+  stream_body<T, R, TY, WAVES, NBUF>(a, a.table ? a.table : tab.e, xcd_remap(blockIdx.x, n), n);
 }
 
 template <typename T, int R, int TY, int WAVES, int NBUF>
@@ -1494,7 +1484,7 @@ void stream_batch(const StepArgs* __restrict__ jobs,
   const int j = find_job(first, njobs, g);
   const StepArgs& a = jobs[j];
   const int n = a.tiles_x * a.tiles_y * a.chunks;
-  stream_body<T, R, TY, WAVES, NBUF>(a, g - first[j], n);
+  stream_body<T, R, TY, WAVES, NBUF>(a, a.table, g - first[j], n);
 }
 
 template <typename T, int R, int TY, int WAVES, int NBUF>
@@ -1544,12 +1534,15 @@ hipError_t launch_tiled(const StepArgs* single, const StepArgs* jobs, const int3
 }
 
 template <typename T, int R, int TY, int WAVES, int NBUF>
-hipError_t launch_stream(const StepArgs* single, const StepArgs* jobs, const int32_t* first, int njobs, int total,
-                         int max_theta, hipStream_t s) {
+hipError_t launch_stream(const StepArgs* single, const ShiftArgs* tab, const StepArgs* jobs, const int32_t* first,
+                         int njobs, int total, int max_theta, hipStream_t s) {
   const size_t table = static_cast<size_t>(max_theta) * 4 * sizeof(int);
   if (single) {
     const int n = single->tiles_x * single->tiles_y * single->chunks;
-    hipLaunchKernelGGL((stream_single<T, R, TY, WAVES, NBUF>), dim3(n), dim3(64 * WAVES), table, s, *single);
+    if (!single->table && !tab) return hipErrorInvalidValue;
+    static const ShiftArgs kNone = {};
+    hipLaunchKernelGGL((stream_single<T, R, TY, WAVES, NBUF>), dim3(n), dim3(64 * WAVES), table, s, *single,
+                       single->table ? kNone : *tab);
   } else {
     hipLaunchKernelGGL((stream_batch<T, R, TY, WAVES, NBUF>), dim3(total), dim3(64 * WAVES), table, s, jobs, first,
                        njobs, total);
@@ -1614,7 +1607,7 @@ hipError_t dispatch_shape(const KernelShape& k, const StepArgs* single, const Sh
   if (k.variant != 0) return hipErrorInvalidValue;
 #define MCL_TRY_STREAM(TY_, WV_, NB_)                                     \
   if (k.tx == 0 && k.ty == TY_ && k.nt == 64 * WV_ && k.nbuf == NB_) \
-    return launch_stream<T, R, TY_, WV_, NB_>(single, jobs, bj, nj, total, max_theta, s);
+    return launch_stream<T, R, TY_, WV_, NB_>(single, tab, jobs, bj, nj, total, max_theta, s);
   MCL_STREAM_SHAPES(MCL_TRY_STREAM)
 #undef MCL_TRY_STREAM
 #define MCL_TRY(TX_, TY_, NT_)                        \
