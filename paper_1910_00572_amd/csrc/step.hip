@@ -123,21 +123,41 @@ struct ProgressPriority {
   }
 };
 
-// Job of global workgroup g: the largest j with first[j] <= g.
-__device__ inline int find_job(const int32_t* __restrict__ first, int njobs, int g) {
+// A batch's job table (StepArgs per job, first workgroup per job) is read
+// through the constant address space with a wave-uniform index: the compiler
+// then uses scalar loads into scalar registers, as for kernel arguments.
+// Read through plain global pointers it treats the loaded arguments as
+// per-lane values and moves the step's whole address arithmetic to the vector
+// unit (the batched step ran at about half the speed of the single one).
+typedef const __attribute__((address_space(4))) int32_t* ConstI32;
+typedef const __attribute__((address_space(4))) StepArgs* ConstArgs;
+
+// Job of global workgroup g: the largest j with first[j] <= g (uniform).
+__device__ inline int find_job(const int32_t* __restrict__ first_p, int njobs, int g) {
+  const ConstI32 first = (ConstI32)first_p;
   int lo = 0, hi = njobs - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
     if (first[mid] <= g) lo = mid;
     else hi = mid - 1;
   }
-  return lo;
+  return __builtin_amdgcn_readfirstlane(lo);
+}
+
+// The arguments of job j, read in place through the constant address space
+// (the step bodies take their argument type as a template parameter), and the
+// workgroup's block index within the job.
+__device__ inline const __attribute__((address_space(4))) StepArgs& job_args(const StepArgs* __restrict__ jobs,
+                                                                            const int32_t* __restrict__ first,
+                                                                            int j, int g, int& blk) {
+  blk = g - ((ConstI32)first)[j];
+  return ((ConstArgs)jobs)[j];
 }
 
 // Run by every thread of the last workgroup to arrive: reduce all partials in
 // a fixed order and update the filter scalars (renormalisation bookkeeping).
-template <int NT>
-__device__ void finalize_step(const StepArgs& a, FilterDev* dev, int nblk, float scale, int cur, double* red_s,
+template <int NT, typename Args>
+__device__ void finalize_step(Args& a, FilterDev* dev, int nblk, float scale, int cur, double* red_s,
                               float* red_m) {
   const int t = threadIdx.x;
   double s = 0.0;
@@ -176,8 +196,8 @@ __device__ void finalize_step(const StepArgs& a, FilterDev* dev, int nblk, float
   }
 }
 
-template <typename T, int R, int TX, int TY, int NT>
-__device__ __forceinline__ void step_body(const StepArgs& a, const int blk, const int nblk) {
+template <typename T, int R, int TX, int TY, int NT, typename Args = const StepArgs>
+__device__ __forceinline__ void step_body(Args& a, const int blk, const int nblk) {
   constexpr int VEC = Store<T>::VEC;
   constexpr int RQ = 4;                      // x halo of the S/Y region, one quad
   constexpr int SC = TX + 2 * RQ;            // S/Y region width
@@ -565,8 +585,8 @@ __device__ inline float from_right(float v) {
   return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x130, 0xf, 0xf, true));
 }
 
-template <typename T, int R, int TY, int WAVES, int NBUF>
-__device__ __forceinline__ void stream_body(const StepArgs& a, const ShiftEntry* __restrict__ tab, const int blk,
+template <typename T, int R, int TY, int WAVES, int NBUF, typename Args = const StepArgs>
+__device__ __forceinline__ void stream_body(Args& a, const ShiftEntry* __restrict__ tab, const int blk,
                                             const int nblk) {
   constexpr int NT = 64 * WAVES;
   constexpr int NS = TY + 2 * R;   // S rows
@@ -888,8 +908,8 @@ __device__ inline void store_row<_Float16>(float v, __amdgpu_buffer_rsrc_t r, ui
 typedef const __attribute__((address_space(4))) ShiftEntry* ConstTable;
 __device__ inline ConstTable const_table(const ShiftEntry* p) { return (ConstTable)p; }
 
-template <typename T, int R, int TY, int WAVES, int NBUF>
-__device__ __forceinline__ void stream2_body(const StepArgs& a, const ShiftEntry* __restrict__ tab, const int blk,
+template <typename T, int R, int TY, int WAVES, int NBUF, typename Args = const StepArgs>
+__device__ __forceinline__ void stream2_body(Args& a, const ShiftEntry* __restrict__ tab, const int blk,
                                              const int nblk) {
   constexpr int NT = 64 * WAVES;
   constexpr int NS = TY + 2 * R;   // S rows
@@ -1178,8 +1198,8 @@ __device__ __forceinline__ void stream2_body(const StepArgs& a, const ShiftEntry
 // once per row (ring layout [slot][row][lane]), so the ring is read
 // (2R + GW) / (GW (2R + 1)) as often as with one channel per wave.  The post-
 // blur weights are folded into the x taps of the wave's rows.
-template <typename T, int R, int TY, int WAVES, int NBUF>
-__device__ __forceinline__ void stream3_body(const StepArgs& a, const ShiftEntry* __restrict__ tab, const int blk,
+template <typename T, int R, int TY, int WAVES, int NBUF, typename Args = const StepArgs>
+__device__ __forceinline__ void stream3_body(Args& a, const ShiftEntry* __restrict__ tab, const int blk,
                                              const int nblk) {
   constexpr int NT = 64 * WAVES;
   constexpr int NS = TY + 2 * R;   // S rows
@@ -1457,9 +1477,10 @@ __global__ __launch_bounds__(NT) void step_batch(const StepArgs* __restrict__ jo
                                                  const int32_t* __restrict__ first, int njobs, int total) {
   const int g = xcd_remap(blockIdx.x, total);
   const int j = find_job(first, njobs, g);
-  const StepArgs& a = jobs[j];
+  int blk = 0;
+  const auto& a = job_args(jobs, first, j, g, blk);
   const int n = a.tiles_x * a.tiles_y * a.chunks;
-  step_body<T, R, TX, TY, NT>(a, g - first[j], n);
+  step_body<T, R, TX, TY, NT>(a, blk, n);
 }
 
 // Eight-wave workgroups aim at six waves per SIMD (three workgroups per
@@ -1482,9 +1503,10 @@ void stream_batch(const StepArgs* __restrict__ jobs,
                                                            const int32_t* __restrict__ first, int njobs, int total) {
   const int g = xcd_remap(blockIdx.x, total);
   const int j = find_job(first, njobs, g);
-  const StepArgs& a = jobs[j];
+  int blk = 0;
+  const auto& a = job_args(jobs, first, j, g, blk);
   const int n = a.tiles_x * a.tiles_y * a.chunks;
-  stream_body<T, R, TY, WAVES, NBUF>(a, a.table, g - first[j], n);
+  stream_body<T, R, TY, WAVES, NBUF>(a, a.table, blk, n);
 }
 
 template <typename T, int R, int TY, int WAVES, int NBUF>
@@ -1499,9 +1521,10 @@ __global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(stre
 void stream2_batch(const StepArgs* __restrict__ jobs, const int32_t* __restrict__ first, int njobs, int total) {
   const int g = xcd_remap(blockIdx.x, total);
   const int j = find_job(first, njobs, g);
-  const StepArgs& a = jobs[j];
+  int blk = 0;
+  const auto& a = job_args(jobs, first, j, g, blk);
   const int n = a.tiles_x * a.tiles_y * a.chunks;
-  stream2_body<T, R, TY, WAVES, NBUF>(a, a.table, g - first[j], n);
+  stream2_body<T, R, TY, WAVES, NBUF>(a, a.table, blk, n);
 }
 
 template <typename T, int R, int TY, int WAVES, int NBUF>
@@ -1516,9 +1539,10 @@ __global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(stre
 void stream3_batch(const StepArgs* __restrict__ jobs, const int32_t* __restrict__ first, int njobs, int total) {
   const int g = xcd_remap(blockIdx.x, total);
   const int j = find_job(first, njobs, g);
-  const StepArgs& a = jobs[j];
+  int blk = 0;
+  const auto& a = job_args(jobs, first, j, g, blk);
   const int n = a.tiles_x * a.tiles_y * a.chunks;
-  stream3_body<T, R, TY, WAVES, NBUF>(a, a.table, g - first[j], n);
+  stream3_body<T, R, TY, WAVES, NBUF>(a, a.table, blk, n);
 }
 
 template <typename T, int R, int TX, int TY, int NT>
