@@ -179,7 +179,8 @@ __host__ __device__ inline int64_t tiled_offset(int64_t cell, int beta, int64_t 
 // step][lane]), so the four waves share it instead of each streaming it from
 // L2; only when all blocks fit one pass (nblocks == NCH) and KPAD > 0.
 template <typename OP, typename T, int MODE, int NCH, int KPAD, bool BL = false>
-__device__ __forceinline__ void scan_gemm_body(const ScanArgs& a, const int tile, const int ntiles) {
+__device__ __forceinline__ void scan_gemm_body(const ScanArgs& a, const int tile, const int ntiles,
+                                               const bool stage = true) {
   constexpr int kNChunk = NCH;  // 32-wide channel blocks held in accumulators at once
   static_assert(!BL || KPAD > 0, "the staged operand needs a compile-time depth");
   __shared__ float red_v[kScanThreads];
@@ -206,7 +207,7 @@ __device__ __forceinline__ void scan_gemm_body(const ScanArgs& a, const int tile
   using Vec = typename Mfma<OP>::Vec;
   constexpr int KSB = KPAD > 0 ? KPAD / KSTEP : 1;  // depth steps of the staged operand
   __shared__ Vec bsh[BL ? NCH * KSB * 64 : 1];
-  if constexpr (BL) {
+  if (BL && stage) {
     // 16-byte pieces of the [npad][kpad] operand, column by column (the
     // global reads are contiguous), written to their MFMA-order slots
     constexpr int PPC = KPAD / HALF;  // pieces per column
@@ -458,6 +459,20 @@ __device__ __forceinline__ void scan_gemm_body(const ScanArgs& a, const int tile
 template <typename OP, typename T, int MODE, int NCH, int KPAD, bool BL = false>
 __global__ __launch_bounds__(kScanThreads) void scan_gemm_kernel(ScanArgs a) {
   scan_gemm_body<OP, T, MODE, NCH, KPAD, BL>(a, blockIdx.x, gridDim.x);
+}
+
+// Persistent form of the staged-operand pass: a workgroup stages the
+// circulant operand once and then takes tiles blockIdx.x, + gridDim.x, ...
+// (two workgroups per compute unit fit the staged operand).  Every tile is
+// computed and published exactly as by scan_gemm_kernel.
+constexpr int kScanPersistBlocks = 512;
+template <typename OP, typename T, int NCH>
+__global__ __launch_bounds__(kScanThreads) void scan_gemm_persist_kernel(ScanArgs a, int ntiles) {
+  bool stage = true;
+  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    scan_gemm_body<OP, T, 0, NCH, 384, true>(a, tile, ntiles, stage);
+    stage = false;
+  }
 }
 
 // The scans of several filters of one map in one launch: every workgroup
@@ -1309,14 +1324,16 @@ hipError_t scan_launch(const ScanLaunch& L, const float* ranges_m, double sigma_
   // channel blocks per pass: all of them when they fit (no recomputation)
   const int nch = std::min(kMaxNChunk, ca.npad / 32);
   // BF16 operands, depth 384, at most three blocks in one pass: the operand
-  // (at most 72 KB) is staged in LDS, two workgroups per compute unit
+  // (at most 72 KB) is staged in LDS, two workgroups per compute unit, each
+  // staging it once for all its tiles
   const bool stage_b = !dout && !t.f32 && t.kpad == 384 && ca.npad / 32 <= 3;
   if (stage_b) {
+    const dim3 gp(std::min(a.tiles, kScanPersistBlocks));
     switch (L.dtype * 8 + nch) {
 #define MCL_GEMM_BL(DT, T_)                                                                                   \
-  case DT * 8 + 1: hipLaunchKernelGGL((scan_gemm_kernel<__bf16, T_, 0, 1, 384, true>), g1, b1, 0, L.stream, a); break; \
-  case DT * 8 + 2: hipLaunchKernelGGL((scan_gemm_kernel<__bf16, T_, 0, 2, 384, true>), g1, b1, 0, L.stream, a); break; \
-  case DT * 8 + 3: hipLaunchKernelGGL((scan_gemm_kernel<__bf16, T_, 0, 3, 384, true>), g1, b1, 0, L.stream, a); break;
+  case DT * 8 + 1: hipLaunchKernelGGL((scan_gemm_persist_kernel<__bf16, T_, 1>), gp, b1, 0, L.stream, a, a.tiles); break; \
+  case DT * 8 + 2: hipLaunchKernelGGL((scan_gemm_persist_kernel<__bf16, T_, 2>), gp, b1, 0, L.stream, a, a.tiles); break; \
+  case DT * 8 + 3: hipLaunchKernelGGL((scan_gemm_persist_kernel<__bf16, T_, 3>), gp, b1, 0, L.stream, a, a.tiles); break;
       MCL_GEMM_BL(0, float)
       MCL_GEMM_BL(1, __bf16)
       MCL_GEMM_BL(2, _Float16)
