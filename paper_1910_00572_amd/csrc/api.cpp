@@ -199,9 +199,11 @@ bool stream_plane_ok(int W, int H, size_t eb) {
 // below are per step; bench-style loops of 300 steps after a warm-up).  Maps
 // of fewer than 512 64 x 16 tiles: the variant-1 streaming kernel (mask in the
 // y taps, theta blur before the x blur, host shift table, emit pipelined
-// against the next warp), 4-row strips, 4 waves, two slice buffers, strips not
-// aligned beyond 4 bytes (512^2 x 72 FP32: 47.8 us against 52.6 us for the
-// variant-0 kernel at its best shape).  Larger maps: the variant-0 streaming
+// against the next warp), 4-row strips, 4 waves, two slice buffers, 56-column
+// strips (32-byte aligned for FP32, 4-byte for 16-bit storage; 512^2 x 72
+// FP32: 1280 workgroups, five waves per SIMD, 41.4 us, against 45.8 us with
+// 57-column strips and 1152 workgroups and 52.6 us for the variant-0 kernel at
+// its best shape).  Larger maps: the variant-0 streaming
 // kernel with 16-row strips, 8 waves and one slice buffer (1024^2 x 128: FP32
 // 333 us with 32-byte aligned strips, BF16 241 us with 4-byte ones; the other
 // shapes and variants measured 247-379 us).  The tiled kernel remains for
@@ -213,7 +215,7 @@ StepShape choose_shape(int W, int H, int T, int R, size_t eb, const int32_t* for
   int sh[7] = {64, 16, 256, 0, 2, 0, kStreamAlignBytes};
   if (stream_plane_ok(W, H, eb)) {
     if (tiled_tiles < 512) {
-      const int v[7] = {0, 4, 256, 1, 2, 1, 4};
+      const int v[7] = {0, 4, 256, 1, 2, 1, eb == 4 ? 32 : 4};
       for (int i = 0; i < 7; ++i) sh[i] = v[i];
     } else {
       const int v[7] = {0, 16, 512, 1, 1, 0, eb == 4 ? 32 : 4};
@@ -532,6 +534,15 @@ mcl_status mcl_init_belief(mcl_map map, const mcl_params* p, void* ws, size_t ws
 
 void mcl_filter_destroy(mcl_filter f) { delete f; }
 
+// Largest whole-cell row shift of a shift table: the streaming kernels address
+// the source rows of strips that no channel shifts past the grid's top edge
+// without per-row checks.
+static int32_t table_ny_max(const ShiftEntry* t, int n) {
+  int32_t m = t[0].ny;
+  for (int k = 1; k < n; ++k) m = std::max(m, t[k].ny);
+  return m;
+}
+
 // Host bookkeeping of one odometry step (Sec. III-A-1, Alg. 1): the heading
 // offset, the sub-cell gate's accumulated displacement, the per-channel shift
 // table f->table (FP64 displacement R(psi_k) [u, v] / cell split into whole
@@ -587,6 +598,7 @@ static hipError_t plan_motion(mcl_filter f, double u, double v, double w, StepAr
       n[2 * k + 1] = static_cast<int32_t>(ny);
       f->table[k] = ShiftEntry{n[2 * k], n[2 * k + 1], 0.f, 0.f};
     }
+    a.ny_max = table_ny_max(f->table, f->T);
     if (dev_ishift) {
       const hipError_t e = launch_write_shifts(n, f->T, f->ishift, s);
       if (e != hipSuccess) return e;
@@ -605,6 +617,7 @@ static hipError_t plan_motion(mcl_filter f, double u, double v, double w, StepAr
     f->table[k] = ShiftEntry{static_cast<int32_t>(fdx), static_cast<int32_t>(fdy), static_cast<float>(dx - fdx),
                              static_cast<float>(dy - fdy)};
   }
+  a.ny_max = table_ny_max(f->table, f->T);
   return hipSuccess;
 }
 

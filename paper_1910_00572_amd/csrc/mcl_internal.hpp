@@ -93,6 +93,7 @@ struct StepArgs {
   int32_t W, H, pitch, n_theta;
   int32_t tiles_x, tiles_y, chunks, chunk_len;
   int32_t strip;              // streaming kernel: output columns per strip
+  int32_t ny_max;             // streaming kernels: largest whole-cell row shift of the table's channels
   int64_t sstride;            // elements per heading slice (H * pitch)
   double u_cells, v_cells;    // odometry in cells, robot frame
   double theta_prev, dtheta;  // heading offset before the step, 2 pi / n_theta

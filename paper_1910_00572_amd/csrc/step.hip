@@ -903,6 +903,13 @@ __device__ inline void store_row<_Float16>(float v, __amdgpu_buffer_rsrc_t r, ui
   __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, static_cast<_Float16>(v)), r, voff, soff, 0);
 }
 
+// Row addressing of a strip's source slices: interior strips address rows
+// from each slice's first row without per-row checks.
+template <bool B>
+struct RowMode {
+  static constexpr bool interior = B;
+};
+
 // The shift table as constant memory: loads at a uniform index become scalar
 // loads (the table is not written while a step runs).
 typedef const __attribute__((address_space(4))) ShiftEntry* ConstTable;
@@ -998,15 +1005,35 @@ __device__ __forceinline__ void stream2_body(Args& a, const ShiftEntry* __restri
   };
   __syncthreads();  // zero lanes written
 
+  // Byte offsets of a slice's rows from its first row (loop-invariant).  In
+  // strips whose slices all start at or below row 0 (no channel shifts its
+  // source rows past the grid's top edge) the load descriptor starts at the
+  // slice's first row and ends with the plane, so rows past the bottom read 0
+  // without per-row checks; the other strips check every row.
+  uint32_t rowoff[NR];
+#pragma unroll
+  for (int r = 0; r < NR; ++r) rowoff[r] = static_cast<uint32_t>(r) * row_bytes;
+  const bool interior = y0 - R - 1 - a.ny_max >= 0;
+  // Cursors: a wave loads and warps relative channels w, w + GW, ... and
+  // emits w - 2R, w - 2R + GW, ... in order, so the physical channel, the ring
+  // slots and the output plane advance by GW per group.
+  int kp_cur = phys(jbeg + w);
+  const int gstep = GW % nth;
+  int pslot = w;
+  int eslot = (w - 2 * R + ((2 * R + GW + RS - 1) / RS) * RS) % RS;
+  const uint32_t out_bytes = static_cast<uint32_t>(min(H - y0, TY)) * row_bytes;
+
   struct Slice {
     float v[NR];
     float fx, fy;
   };
   // Source rows of relative channel c, one group ahead (no branch around the
   // loads: channels past the end read through an empty descriptor).
-  auto load_slice = [&](int c, Slice& sl) {
+  auto load_slice = [&](auto mode, int c, Slice& sl) {
     const bool live = c < count;
-    const int kp = phys(jbeg + (live ? c : 0));
+    const int kp = kp_cur;
+    kp_cur += gstep;
+    if (kp_cur >= nth) kp_cur -= nth;
     // uniform index into a table that no workgroup writes: scalar loads
     const ConstTable e = const_table(tab) + kp;
     const int nx = __builtin_amdgcn_readfirstlane(e->nx);
@@ -1017,24 +1044,36 @@ __device__ __forceinline__ void stream2_body(Args& a, const ShiftEntry* __restri
     const uint32_t loff = static_cast<unsigned>(cx) < static_cast<unsigned>(pitch) ? static_cast<uint32_t>(cx) * EB
                                                                                     : kColOut;
     const int sy0 = y0 - R - ny - 1;
-    const __amdgpu_buffer_rsrc_t rs = buf_rsrc(bin + static_cast<int64_t>(kp) * sstride, live ? plane_bytes : 0u);
+    const T* plane = bin + static_cast<int64_t>(kp) * sstride;
+    if constexpr (decltype(mode)::interior) {
+      const uint32_t rows_in = static_cast<uint32_t>(max(H - sy0, 0));
+      const __amdgpu_buffer_rsrc_t rs =
+          buf_rsrc(plane + static_cast<int64_t>(sy0) * pitch, live ? rows_in * row_bytes : 0u);
 #pragma unroll
-    for (int r = 0; r < NR; ++r) {
-      const int sy = sy0 + r;
-      const uint32_t roff = static_cast<unsigned>(sy) < static_cast<unsigned>(H) ? static_cast<uint32_t>(sy) * row_bytes
-                                                                                 : kRowOut;
-      sl.v[r] = load_row<T>(rs, loff, roff);
+      for (int r = 0; r < NR; ++r) sl.v[r] = load_row<T>(rs, loff, rowoff[r]);
+    } else {
+      const __amdgpu_buffer_rsrc_t rs = buf_rsrc(plane, live ? plane_bytes : 0u);
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        const int sy = sy0 + r;
+        const uint32_t roff = static_cast<unsigned>(sy) < static_cast<unsigned>(H)
+                                  ? static_cast<uint32_t>(sy) * row_bytes
+                                  : kRowOut;
+        sl.v[r] = load_row<T>(rs, loff, roff);
+      }
     }
   };
-  // bilinear warp and masked y blur of relative channel c into its ring slot
-  auto process = [&](int c, Slice& sl) {
+  // bilinear warp and masked y blur of the wave's next channel into its ring slot
+  auto process = [&](Slice& sl) {
     float(&vv)[NR] = sl.v;
     const float fx = sl.fx, fy = sl.fy;
 #pragma unroll
     for (int r = 0; r < NR; ++r) vv[r] = fmaf(fx, from_left(vv[r]) - vv[r], vv[r]);
 #pragma unroll
     for (int r = 0; r < NS; ++r) vv[r] = fmaf(fy, vv[r] - vv[r + 1], vv[r + 1]);
-    float* slot = &ring[c % RS][lane][0];
+    float* slot = &ring[pslot][lane][0];
+    pslot += GW;
+    if (pslot >= RS) pslot -= RS;
 #pragma unroll
     for (int o4 = 0; o4 < TY; o4 += 4) {
       float p4[4];
@@ -1057,12 +1096,11 @@ __device__ __forceinline__ void stream2_body(Args& a, const ShiftEntry* __restri
   // blurs along x from the neighbouring lanes, applies the post-blur weights,
   // stores and reduces.
   typedef float4 RingRead[TY / 4][TAPS];
-  auto emit_read = [&](int g, RingRead& rv) {
-    const int krel = GW * g - 2 * R + w;
-    // ring slots of channels krel .. krel + 2R; krel >= -(2R + GW) (padding
-    // emits), so a multiple of RS keeps the modulus non-negative
-    constexpr int OFF = ((2 * R + GW + RS - 1) / RS) * RS;
-    int slot = (krel + OFF) % RS;
+  auto emit_read = [&](RingRead& rv) {
+    // ring slots of channels krel .. krel + 2R, krel = GW g - 2R + w
+    int slot = eslot;
+    eslot += GW;
+    if (eslot >= RS) eslot -= RS;
 #pragma unroll
     for (int l = 0; l < TAPS; ++l) {
 #pragma unroll
@@ -1074,7 +1112,9 @@ __device__ __forceinline__ void stream2_body(Args& a, const ShiftEntry* __restri
     const int krel = GW * g - 2 * R + w;
     const bool live = krel >= 0 && krel < nk;
     const int ko = kbeg + (live ? krel : 0);
-    const __amdgpu_buffer_rsrc_t rs = buf_rsrc(bout + static_cast<int64_t>(ko) * sstride, live ? plane_bytes : 0u);
+    // the descriptor covers the strip's rows inside the grid
+    const __amdgpu_buffer_rsrc_t rs =
+        buf_rsrc(bout + static_cast<int64_t>(ko) * sstride + static_cast<int64_t>(y0) * pitch, live ? out_bytes : 0u);
 #pragma unroll
     for (int b = 0; b < TY / 4; ++b) {
       float z[4] = {0.f, 0.f, 0.f, 0.f};
@@ -1111,9 +1151,7 @@ __device__ __forceinline__ void stream2_body(Args& a, const ShiftEntry* __restri
         const float ov = o4[e] * wreg[o];
         es += ov;
         em = fmaxf(em, ov);
-        const int y = y0 + o;
-        const uint32_t roff = y < H ? static_cast<uint32_t>(y) * row_bytes : kRowOut;
-        store_row<T>(ov, rs, soff, roff);
+        store_row<T>(ov, rs, soff, rowoff[o]);
       }
     }
     if (live) {
@@ -1123,50 +1161,56 @@ __device__ __forceinline__ void stream2_body(Args& a, const ShiftEntry* __restri
   };
 
   auto ch = [&](int g) { return GW * g + w; };
-  // Software pipeline: between two barriers a wave emits group g - 1 and
-  // warps group g (their ring slots are distinct), so the emit's LDS reads
-  // are in flight during the warp.  Channels past the end (the last groups)
-  // load through empty descriptors and their emits store nothing.
-  if constexpr (NBUF == 2) {
-    const int G = (((count + GW - 1) / GW) + 1) & ~1;  // even: the last may be padding
-    const ProgressPriority prio(G);
-    Slice sA, sB;
-    RingRead rv;
-    load_slice(ch(0), sA);
-    load_slice(ch(1), sB);
-    process(ch(0), sA);
-    __syncthreads();
-    for (int g = 1; g <= G; g += 2) {
-      prio.at(g);
-      load_slice(ch(g + 1), sA);
-      emit_read(g - 1, rv);
-      process(ch(g), sB);
-      emit_finish(g - 1, rv);
+  auto pipeline = [&](auto mode) {
+    // Software pipeline: between two barriers a wave emits group g - 1 and
+    // warps group g (their ring slots are distinct), so the emit's LDS reads
+    // are in flight during the warp.  Channels past the end (the last groups)
+    // load through empty descriptors and their emits store nothing.
+    if constexpr (NBUF == 2) {
+      const int G = (((count + GW - 1) / GW) + 1) & ~1;  // even: the last may be padding
+      const ProgressPriority prio(G);
+      Slice sA, sB;
+      RingRead rv;
+      load_slice(mode, ch(0), sA);
+      load_slice(mode, ch(1), sB);
+      process(sA);
       __syncthreads();
-      load_slice(ch(g + 2), sB);
-      emit_read(g, rv);
-      process(ch(g + 1), sA);
-      emit_finish(g, rv);
+      for (int g = 1; g <= G; g += 2) {
+        prio.at(g);
+        load_slice(mode, ch(g + 1), sA);
+        emit_read(rv);
+        process(sB);
+        emit_finish(g - 1, rv);
+        __syncthreads();
+        load_slice(mode, ch(g + 2), sB);
+        emit_read(rv);
+        process(sA);
+        emit_finish(g, rv);
+        __syncthreads();
+      }
+    } else {
+      const int G = (count + GW - 1) / GW;
+      const ProgressPriority prio(G);
+      Slice sA;
+      RingRead rv;
+      load_slice(mode, ch(0), sA);
+      process(sA);
+      load_slice(mode, ch(1), sA);
       __syncthreads();
+      for (int g = 1; g <= G; ++g) {
+        prio.at(g);
+        emit_read(rv);
+        process(sA);
+        load_slice(mode, ch(g + 1), sA);
+        emit_finish(g - 1, rv);
+        __syncthreads();
+      }
     }
-  } else {
-    const int G = (count + GW - 1) / GW;
-    const ProgressPriority prio(G);
-    Slice sA;
-    RingRead rv;
-    load_slice(ch(0), sA);
-    process(ch(0), sA);
-    load_slice(ch(1), sA);
-    __syncthreads();
-    for (int g = 1; g <= G; ++g) {
-      prio.at(g);
-      emit_read(g - 1, rv);
-      process(ch(g), sA);
-      load_slice(ch(g + 1), sA);
-      emit_finish(g - 1, rv);
-      __syncthreads();
-    }
-  }
+  };
+  if (interior)
+    pipeline(RowMode<true>{});
+  else
+    pipeline(RowMode<false>{});
   __syncthreads();  // the ring becomes the reduction buffer
 
   red_s[t] = static_cast<double>(psum);
