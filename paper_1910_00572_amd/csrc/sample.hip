@@ -232,8 +232,12 @@ __global__ __launch_bounds__(64) void dither_wave_kernel(DitherArgs a) {
         ua[c] = __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, hist[c]), 0x13C, 0xf, 0xf,
                                                                    true));
       const int i0 = p * K - (K + 1) * j;
-      // a row past the last reads as a column past the end
-      const uint32_t wlim = j < H ? static_cast<uint32_t>(W) : 0u;
+      // a row past the last reads as a column past the end; the empty asm
+      // keeps the limit a plain register, so each cell is tested with one
+      // vector compare (left visible, the compiler splits the test into a
+      // per-cell compare and a scalar AND with the row condition)
+      uint32_t wlim = j < H ? static_cast<uint32_t>(W) : 0u;
+      asm volatile("" : "+v"(wlim));
       // mask byte of cell c: offset base + c, the c in the instruction's scalar
       // offset; a cell outside the image selects kOut - c instead.  At 16
       // cells per phase the compiler's schedule of that form measured slower

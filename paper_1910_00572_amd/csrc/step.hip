@@ -492,6 +492,7 @@ __device__ __forceinline__ void step_body(Args& a, const int blk, const int nblk
   red_s[t] = static_cast<double>(psum);
   red_m[t] = pmax;
   __syncthreads();
+  static_assert((NT & (NT - 1)) == 0, "the tree reduction needs a power-of-two workgroup");
 #pragma unroll
   for (int s = NT / 2; s > 0; s >>= 1) {
     if (t < s) {
@@ -576,6 +577,42 @@ __device__ inline __amdgpu_buffer_rsrc_t buf_rsrc(const void* base, uint32_t byt
 // returns 0, the store is dropped) exactly when the row or the column is.
 constexpr uint32_t kRowOut = 1u << 30;
 constexpr uint32_t kColOut = 1u << 31;
+
+template <typename T>
+__device__ inline float load_row(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff);
+template <>
+__device__ inline float load_row<float>(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+template <>
+__device__ inline float load_row<__bf16>(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+  return __uint_as_float(static_cast<uint32_t>(__builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0)) << 16);
+}
+template <>
+__device__ inline float load_row<_Float16>(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+  return static_cast<float>(__builtin_bit_cast(_Float16, __builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0)));
+}
+template <typename T>
+__device__ inline void store_row(float v, __amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff);
+template <>
+__device__ inline void store_row<float>(float v, __amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, voff, soff, 0);
+}
+template <>
+__device__ inline void store_row<__bf16>(float v, __amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+  __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, static_cast<__bf16>(v)), r, voff, soff, 0);
+}
+template <>
+__device__ inline void store_row<_Float16>(float v, __amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+  __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, static_cast<_Float16>(v)), r, voff, soff, 0);
+}
+
+// Row addressing of a strip's source slices: interior strips address rows
+// from each slice's first row without per-row checks.
+template <bool B>
+struct RowMode {
+  static constexpr bool interior = B;
+};
 
 // lane i receives lane i-1 / i+1; lanes without a source receive 0
 __device__ inline float from_left(float v) {
@@ -683,6 +720,19 @@ __device__ __forceinline__ void stream_body(Args& a, const ShiftEntry* __restric
   };
   __syncthreads();  // shift table ready
 
+  // Row offsets from a slice's first row, the interior-strip test and the
+  // load cursor, as in the variant-1 kernel below: strips whose slices all
+  // start at or below row 0 address rows from each slice's first row through
+  // the buffer instructions' scalar offset, without per-row checks.
+  uint32_t rowoff[NR];
+#pragma unroll
+  for (int r = 0; r < NR; ++r) rowoff[r] = static_cast<uint32_t>(r) * row_bytes;
+  const bool interior = y0 - R - 1 - a.ny_max >= 0;
+  int kp_cur = phys(jbeg + w);
+  const int gstep = GW % nth;
+  int pslot = w;
+  const uint32_t out_bytes = static_cast<uint32_t>(min(H - y0, TY)) * row_bytes;
+
   // Source rows of channel jrel and its fractional shift (read here, one
   // group ahead, so that process() starts without an LDS round trip).
   //
@@ -697,9 +747,11 @@ __device__ __forceinline__ void stream_body(Args& a, const ShiftEntry* __restric
     float v[NR];
     float fx, fy;
   };
-  auto load_slice = [&](int jrel, Slice& sl) {
+  auto load_slice = [&](auto mode, int jrel, Slice& sl) {
     const bool live = jrel < count;
-    const int kp = phys(jbeg + (live ? jrel : 0));
+    const int kp = kp_cur;
+    kp_cur += gstep;
+    if (kp_cur >= nth) kp_cur -= nth;
     const int nx = __builtin_amdgcn_readfirstlane(pnx[kp]);
     const int ny = __builtin_amdgcn_readfirstlane(pny[kp]);
     sl.fx = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, pfx[kp])));
@@ -708,23 +760,35 @@ __device__ __forceinline__ void stream_body(Args& a, const ShiftEntry* __restric
     const uint32_t loff = static_cast<unsigned>(c) < static_cast<unsigned>(pitch) ? static_cast<uint32_t>(c) * EB
                                                                                    : kColOut;
     const int sy0 = y0 - R - ny - 1;
-    const __amdgpu_buffer_rsrc_t rs = buf_rsrc(bin + static_cast<int64_t>(kp) * sstride, live ? plane_bytes : 0u);
+    const T* plane = bin + static_cast<int64_t>(kp) * sstride;
+    if constexpr (decltype(mode)::interior) {
+      const uint32_t rows_in = static_cast<uint32_t>(max(H - sy0, 0));
+      const __amdgpu_buffer_rsrc_t rs =
+          buf_rsrc(plane + static_cast<int64_t>(sy0) * pitch, live ? rows_in * row_bytes : 0u);
 #pragma unroll
-    for (int r = 0; r < NR; ++r) {
-      const int sy = sy0 + r;
-      const uint32_t roff = static_cast<unsigned>(sy) < static_cast<unsigned>(H) ? static_cast<uint32_t>(sy) * row_bytes
-                                                                                 : kRowOut;
-      sl.v[r] = Elt<T>::load(rs, loff + roff);
+      for (int r = 0; r < NR; ++r) sl.v[r] = load_row<T>(rs, loff, rowoff[r]);
+    } else {
+      const __amdgpu_buffer_rsrc_t rs = buf_rsrc(plane, live ? plane_bytes : 0u);
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        const int sy = sy0 + r;
+        const uint32_t roff = static_cast<unsigned>(sy) < static_cast<unsigned>(H)
+                                  ? static_cast<uint32_t>(sy) * row_bytes
+                                  : kRowOut;
+        sl.v[r] = load_row<T>(rs, loff, roff);
+      }
     }
   };
-  auto process = [&](int jrel, Slice& sl) {
+  auto process = [&](Slice& sl) {
     float(&vv)[NR] = sl.v;
     const float fx = sl.fx, fy = sl.fy;
 #pragma unroll
     for (int r = 0; r < NR; ++r) vv[r] = fmaf(fx, from_left(vv[r]) - vv[r], vv[r]);
 #pragma unroll
     for (int r = 0; r < NS; ++r) vv[r] = fmaf(fy, vv[r] - vv[r + 1], vv[r + 1]) * mreg[r];
-    float* slot = &ring[jrel % RS][lane][0];
+    float* slot = &ring[pslot][lane][0];
+    pslot += GW;
+    if (pslot >= RS) pslot -= RS;
 #pragma unroll
     for (int o4 = 0; o4 < TY; o4 += 4) {
       float p4[4];
@@ -757,7 +821,9 @@ __device__ __forceinline__ void stream_body(Args& a, const ShiftEntry* __restric
     const int krel = GW * g - 2 * R + w;
     const bool live = krel >= 0 && krel < nk;
     const int ko = kbeg + (live ? krel : 0);
-    const __amdgpu_buffer_rsrc_t rs = buf_rsrc(bout + static_cast<int64_t>(ko) * sstride, live ? plane_bytes : 0u);
+    // the descriptor covers the strip's rows inside the grid
+    const __amdgpu_buffer_rsrc_t rs =
+        buf_rsrc(bout + static_cast<int64_t>(ko) * sstride + static_cast<int64_t>(y0) * pitch, live ? out_bytes : 0u);
     // ring slots of channels krel .. krel + 2R; krel >= -(2R + GW) (padding
     // emits), so a multiple of RS keeps the modulus non-negative
     constexpr int OFF = ((2 * R + GW + RS - 1) / RS) * RS;
@@ -791,9 +857,7 @@ __device__ __forceinline__ void stream_body(Args& a, const ShiftEntry* __restric
           const float ovk = live ? ov : 0.f;
           psum += ovk;
           pmax = fmaxf(pmax, ovk);
-          const int y = y0 + o;
-          const uint32_t roff = y < H ? static_cast<uint32_t>(y) * row_bytes : kRowOut;
-          Elt<T>::store(ov, rs, soff + roff);
+          store_row<T>(ov, rs, soff, rowoff[o]);
         }
       }
     }
@@ -808,41 +872,48 @@ __device__ __forceinline__ void stream_body(Args& a, const ShiftEntry* __restric
   // next slice is loaded into the registers the current one just left, one
   // emit ahead (fewer registers, for more waves per SIMD).
   auto ch = [&](int g) { return GW * g + w; };
-  if constexpr (NBUF == 2) {
-    const int G = (((count + GW - 1) / GW) + 1) & ~1;  // even: the last may be padding
-    Slice sA, sB;
-    load_slice(ch(0), sA);
-    emit(-1);
-    for (int g = 0; g < G; g += 2) {
-      load_slice(ch(g + 1), sB);
-      process(ch(g), sA);
-      __syncthreads();
-      emit(g);
-      if (!ONE_BARRIER) __syncthreads();
-      load_slice(ch(g + 2), sA);
-      process(ch(g + 1), sB);
-      __syncthreads();
-      emit(g + 1);
-      if (!ONE_BARRIER) __syncthreads();
+  auto pipeline = [&](auto mode) {
+    if constexpr (NBUF == 2) {
+      const int G = (((count + GW - 1) / GW) + 1) & ~1;  // even: the last may be padding
+      Slice sA, sB;
+      load_slice(mode, ch(0), sA);
+      emit(-1);
+      for (int g = 0; g < G; g += 2) {
+        load_slice(mode, ch(g + 1), sB);
+        process(sA);
+        __syncthreads();
+        emit(g);
+        if (!ONE_BARRIER) __syncthreads();
+        load_slice(mode, ch(g + 2), sA);
+        process(sB);
+        __syncthreads();
+        emit(g + 1);
+        if (!ONE_BARRIER) __syncthreads();
+      }
+    } else {
+      const int G = (count + GW - 1) / GW;
+      Slice sA;
+      load_slice(mode, ch(0), sA);
+      emit(-1);
+      for (int g = 0; g < G; ++g) {
+        process(sA);
+        load_slice(mode, ch(g + 1), sA);
+        __syncthreads();
+        emit(g);
+        if (!ONE_BARRIER) __syncthreads();
+      }
     }
-  } else {
-    const int G = (count + GW - 1) / GW;
-    Slice sA;
-    load_slice(ch(0), sA);
-    emit(-1);
-    for (int g = 0; g < G; ++g) {
-      process(ch(g), sA);
-      load_slice(ch(g + 1), sA);
-      __syncthreads();
-      emit(g);
-      if (!ONE_BARRIER) __syncthreads();
-    }
-  }
+  };
+  if (interior)
+    pipeline(RowMode<true>{});
+  else
+    pipeline(RowMode<false>{});
   __syncthreads();  // the ring becomes the reduction buffer
 
   red_s[t] = static_cast<double>(psum);
   red_m[t] = pmax;
   __syncthreads();
+  static_assert((NT & (NT - 1)) == 0, "the tree reduction needs a power-of-two workgroup");
 #pragma unroll
   for (int s = NT / 2; s > 0; s >>= 1) {
     if (t < s) {
@@ -874,42 +945,6 @@ __device__ __forceinline__ void stream_body(Args& a, const ShiftEntry* __restric
 // The shift table (whole-cell offsets and bilinear fractions per channel) is
 // computed on the host and read with scalar loads; row offsets go in the
 // buffer instructions' scalar offset, which the range check includes.
-template <typename T>
-__device__ inline float load_row(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff);
-template <>
-__device__ inline float load_row<float>(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
-}
-template <>
-__device__ inline float load_row<__bf16>(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
-  return __uint_as_float(static_cast<uint32_t>(__builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0)) << 16);
-}
-template <>
-__device__ inline float load_row<_Float16>(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
-  return static_cast<float>(__builtin_bit_cast(_Float16, __builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0)));
-}
-template <typename T>
-__device__ inline void store_row(float v, __amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff);
-template <>
-__device__ inline void store_row<float>(float v, __amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
-  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, voff, soff, 0);
-}
-template <>
-__device__ inline void store_row<__bf16>(float v, __amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
-  __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, static_cast<__bf16>(v)), r, voff, soff, 0);
-}
-template <>
-__device__ inline void store_row<_Float16>(float v, __amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
-  __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, static_cast<_Float16>(v)), r, voff, soff, 0);
-}
-
-// Row addressing of a strip's source slices: interior strips address rows
-// from each slice's first row without per-row checks.
-template <bool B>
-struct RowMode {
-  static constexpr bool interior = B;
-};
-
 // The shift table as constant memory: loads at a uniform index become scalar
 // loads (the table is not written while a step runs).
 typedef const __attribute__((address_space(4))) ShiftEntry* ConstTable;
@@ -1216,6 +1251,7 @@ __device__ __forceinline__ void stream2_body(Args& a, const ShiftEntry* __restri
   red_s[t] = static_cast<double>(psum);
   red_m[t] = pmax;
   __syncthreads();
+  static_assert((NT & (NT - 1)) == 0, "the tree reduction needs a power-of-two workgroup");
 #pragma unroll
   for (int s = NT / 2; s > 0; s >>= 1) {
     if (t < s) {
@@ -1492,6 +1528,7 @@ __device__ __forceinline__ void stream3_body(Args& a, const ShiftEntry* __restri
   red_s[t] = static_cast<double>(psum);
   red_m[t] = pmax;
   __syncthreads();
+  static_assert((NT & (NT - 1)) == 0, "the tree reduction needs a power-of-two workgroup");
 #pragma unroll
   for (int s = NT / 2; s > 0; s >>= 1) {
     if (t < s) {
