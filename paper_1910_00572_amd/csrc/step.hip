@@ -967,8 +967,18 @@ __device__ __forceinline__ void stream2_body(Args& a, const ShiftEntry* __restri
   static_assert(TY % 4 == 0, "rows per strip must be a multiple of 4");
   static_assert(NBUF == 1 || NBUF == 2, "one or two source-slice buffers");
   static_assert(sizeof(float) * RS * 64 * LP >= NT * (sizeof(double) + sizeof(float)), "reduction fits the ring");
+  // Full-circle schedule, for a workgroup that holds every heading: each
+  // channel is warped once, in order, and the emits lag the warps by LW
+  // groups, so that no group is padding.  The outputs next to the end of the
+  // circle read the first 2R channels' y-blurred rows from RSW + 0 .. 2R - 1,
+  // which nothing overwrites; the other channels rotate through RSW slots.
+  constexpr bool kCircle = NBUF == 2 && TY == 4;
+  constexpr int LW = 1 + (2 * R + GW - 1) / GW;
+  constexpr int RSW = (LW + 1) * GW <= 16 ? 16 : 32;
+  static_assert((LW + 1) * GW <= RSW, "the circle's live channels fit its slots");
+  constexpr int RSA = kCircle ? (RS > RSW + 2 * R ? RS : RSW + 2 * R) : RS;
 
-  __shared__ __attribute__((aligned(16))) float ring[RS][64][LP];
+  __shared__ __attribute__((aligned(16))) float ring[RSA][64][LP];
   __shared__ __attribute__((aligned(16))) float zrow[WAVES][ZL][LP];
   __shared__ int last_flag;
   double* red_s = reinterpret_cast<double*>(&ring[0][0][0]);
@@ -1057,6 +1067,8 @@ __device__ __forceinline__ void stream2_body(Args& a, const ShiftEntry* __restri
   int pslot = w;
   int eslot = (w - 2 * R + ((2 * R + GW + RS - 1) / RS) * RS) % RS;
   const uint32_t out_bytes = static_cast<uint32_t>(min(H - y0, TY)) * row_bytes;
+  const bool circle = kCircle && a.chunks == 1 && nth >= 2 * R + 2 * GW;
+  int lim = count;  // relative channels below lim are warped
 
   struct Slice {
     float v[NR];
@@ -1065,7 +1077,7 @@ __device__ __forceinline__ void stream2_body(Args& a, const ShiftEntry* __restri
   // Source rows of relative channel c, one group ahead (no branch around the
   // loads: channels past the end read through an empty descriptor).
   auto load_slice = [&](auto mode, int c, Slice& sl) {
-    const bool live = c < count;
+    const bool live = c < lim;
     const int kp = kp_cur;
     kp_cur += gstep;
     if (kp_cur >= nth) kp_cur -= nth;
@@ -1098,17 +1110,15 @@ __device__ __forceinline__ void stream2_body(Args& a, const ShiftEntry* __restri
       }
     }
   };
-  // bilinear warp and masked y blur of the wave's next channel into its ring slot
-  auto process = [&](Slice& sl) {
+  // bilinear warp and masked y blur of a slice into a ring slot (and, when
+  // keep is set, into a reserved slot as well)
+  auto process_into = [&](Slice& sl, float* slot, float* keep) {
     float(&vv)[NR] = sl.v;
     const float fx = sl.fx, fy = sl.fy;
 #pragma unroll
     for (int r = 0; r < NR; ++r) vv[r] = fmaf(fx, from_left(vv[r]) - vv[r], vv[r]);
 #pragma unroll
     for (int r = 0; r < NS; ++r) vv[r] = fmaf(fy, vv[r] - vv[r + 1], vv[r + 1]);
-    float* slot = &ring[pslot][lane][0];
-    pslot += GW;
-    if (pslot >= RS) pslot -= RS;
 #pragma unroll
     for (int o4 = 0; o4 < TY; o4 += 4) {
       float p4[4];
@@ -1121,7 +1131,15 @@ __device__ __forceinline__ void stream2_body(Args& a, const ShiftEntry* __restri
         p4[q] = yv;
       }
       *reinterpret_cast<float4*>(slot + o4) = make_float4(p4[0], p4[1], p4[2], p4[3]);
+      if (keep) *reinterpret_cast<float4*>(keep + o4) = make_float4(p4[0], p4[1], p4[2], p4[3]);
     }
+  };
+  // the wave's next channel of the chunk schedule
+  auto process = [&](Slice& sl) {
+    float* slot = &ring[pslot][lane][0];
+    pslot += GW;
+    if (pslot >= RS) pslot -= RS;
+    process_into(sl, slot, nullptr);
   };
   float psum = 0.f, pmax = 0.f;
   float* zmine = &zrow[w][lane + R][0];
@@ -1143,13 +1161,8 @@ __device__ __forceinline__ void stream2_body(Args& a, const ShiftEntry* __restri
       slot = slot + 1 == RS ? 0 : slot + 1;
     }
   };
-  auto emit_finish = [&](int g, RingRead& rv) {
-    const int krel = GW * g - 2 * R + w;
-    const bool live = krel >= 0 && krel < nk;
-    const int ko = kbeg + (live ? krel : 0);
-    // the descriptor covers the strip's rows inside the grid
-    const __amdgpu_buffer_rsrc_t rs =
-        buf_rsrc(bout + static_cast<int64_t>(ko) * sstride + static_cast<int64_t>(y0) * pitch, live ? out_bytes : 0u);
+  // theta blur of the group's ring rows into the wave's x-blur row
+  auto emit_theta = [&](RingRead& rv) {
 #pragma unroll
     for (int b = 0; b < TY / 4; ++b) {
       float z[4] = {0.f, 0.f, 0.f, 0.f};
@@ -1162,6 +1175,48 @@ __device__ __forceinline__ void stream2_body(Args& a, const ShiftEntry* __restri
       }
       *reinterpret_cast<float4*>(zmine + 4 * b) = make_float4(z[0], z[1], z[2], z[3]);
     }
+  };
+  // the neighbouring lanes' theta-blurred values of rows ob .. ob + 3
+  auto emit_x_read = [&](int ob, float4 (&zv)[TAPS]) {
+#pragma unroll
+    for (int l = 0; l < TAPS; ++l) zv[l] = *reinterpret_cast<const float4*>(zmine + (l - R) * LP + ob);
+  };
+  // output channel krel (relative to the chunk; stores and sums nothing
+  // outside it): the descriptor covers the strip's rows inside the grid
+  auto out_rsrc = [&](const int krel) {
+    const bool live = krel >= 0 && krel < nk;
+    const int ko = kbeg + (live ? krel : 0);
+    return buf_rsrc(bout + static_cast<int64_t>(ko) * sstride + static_cast<int64_t>(y0) * pitch,
+                    live ? out_bytes : 0u);
+  };
+  // x blur of rows ob .. ob + 3, post-blur weights, stores and the sums
+  auto emit_x_finish = [&](int ob, const __amdgpu_buffer_rsrc_t rs, float4 (&zv)[TAPS], float& es, float& em) {
+    float o4[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int l = 0; l < TAPS; ++l) {
+      o4[0] = fmaf(gx[l], zv[l].x, o4[0]);
+      o4[1] = fmaf(gx[l], zv[l].y, o4[1]);
+      o4[2] = fmaf(gx[l], zv[l].z, o4[2]);
+      o4[3] = fmaf(gx[l], zv[l].w, o4[3]);
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int o = ob + e;
+      const float ov = o4[e] * wreg[o];
+      es += ov;
+      em = fmaxf(em, ov);
+      store_row<T>(ov, rs, soff, rowoff[o]);
+    }
+  };
+  auto emit_sum = [&](const int krel, float es, float em) {
+    if (krel >= 0 && krel < nk) {
+      psum += es;
+      pmax = fmaxf(pmax, em);
+    }
+  };
+  auto emit_finish_k = [&](const int krel, RingRead& rv) {
+    const __amdgpu_buffer_rsrc_t rs = out_rsrc(krel);
+    emit_theta(rv);
     // the x-blur row is written and read by this wave only: LDS operations
     // of one wave complete in order, so a wave-scope fence suffices
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -1170,32 +1225,86 @@ __device__ __forceinline__ void stream2_body(Args& a, const ShiftEntry* __restri
 #pragma unroll
     for (int ob = 0; ob < TY; ob += 4) {
       float4 zv[TAPS];
-#pragma unroll
-      for (int l = 0; l < TAPS; ++l) zv[l] = *reinterpret_cast<const float4*>(zmine + (l - R) * LP + ob);
-      float o4[4] = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-      for (int l = 0; l < TAPS; ++l) {
-        o4[0] = fmaf(gx[l], zv[l].x, o4[0]);
-        o4[1] = fmaf(gx[l], zv[l].y, o4[1]);
-        o4[2] = fmaf(gx[l], zv[l].z, o4[2]);
-        o4[3] = fmaf(gx[l], zv[l].w, o4[3]);
-      }
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int o = ob + e;
-        const float ov = o4[e] * wreg[o];
-        es += ov;
-        em = fmaxf(em, ov);
-        store_row<T>(ov, rs, soff, rowoff[o]);
-      }
+      emit_x_read(ob, zv);
+      emit_x_finish(ob, rs, zv, es, em);
     }
-    if (live) {
-      psum += es;
-      pmax = fmaxf(pmax, em);
+    emit_sum(krel, es, em);
+  };
+
+  auto emit_finish = [&](int g, RingRead& rv) { emit_finish_k(GW * g - 2 * R + w, rv); };
+  // Full-circle schedule: relative channel c (physical c - R) lives in slot
+  // c mod RSW, the first 2R also in RSW + c; output k reads relative k .. k + 2R.
+  auto process_circle = [&](int h, Slice& sl) {
+    const int c = GW * h + w;
+    process_into(sl, &ring[c & (RSW - 1)][lane][0], c < 2 * R ? &ring[RSW + c][lane][0] : nullptr);
+  };
+  auto emit_read_circle = [&](int e, RingRead& rv) {
+    // outputs past the last heading store nothing; clamping their first
+    // channel keeps every slot index below RSW + 2R
+    const int c0 = min(GW * e + w, nth - 1);
+#pragma unroll
+    for (int l = 0; l < TAPS; ++l) {
+      const int c = c0 + l;
+      const int slot = c < nth ? (c & (RSW - 1)) : RSW + (c - nth);
+#pragma unroll
+      for (int b = 0; b < TY / 4; ++b) rv[b][l] = *reinterpret_cast<const float4*>(&ring[slot][lane][4 * b]);
     }
   };
 
   auto ch = [&](int g) { return GW * g + w; };
+  auto pipeline_circle = [&](auto mode) {
+    if constexpr (kCircle) {
+      lim = nth;
+      const int GP = (nth + GW - 1) / GW;  // warp groups; emit group e runs with warp group e + LW
+      const ProgressPriority prio(GP + LW);
+      Slice sA, sB;
+      RingRead rv;
+      // group h's slice is sA for even h, sB for odd h; it is loaded while
+      // group h - 1 is warped
+      // stage h: load group h + 1, warp group h, emit group h - LW
+      auto step = [&](int h, Slice& cur_sl, Slice& next_sl, bool emit, bool warp) {
+        if (warp) load_slice(mode, ch(h + 1), next_sl);
+        if (emit) emit_read_circle(h - LW, rv);
+        if (warp) process_circle(h, cur_sl);
+        if (emit) emit_finish_k(GW * (h - LW) + w, rv);
+        __syncthreads();
+      };
+      load_slice(mode, ch(0), sA);
+      load_slice(mode, ch(1), sB);
+      process_circle(0, sA);
+      __syncthreads();
+#pragma unroll
+      for (int h = 1; h < LW; ++h) {
+        if (h & 1)
+          step(h, sB, sA, false, true);
+        else
+          step(h, sA, sB, false, true);
+      }
+      int h = LW;
+      for (; h + 1 < GP; h += 2) {
+        prio.at(h);
+        if constexpr (LW & 1) {
+          step(h, sB, sA, true, true);
+          step(h + 1, sA, sB, true, true);
+        } else {
+          step(h, sA, sB, true, true);
+          step(h + 1, sB, sA, true, true);
+        }
+      }
+      if (h < GP) {
+        if constexpr (LW & 1)
+          step(h, sB, sA, true, true);
+        else
+          step(h, sA, sB, true, true);
+        ++h;
+      }
+#pragma unroll
+      for (int i = 0; i < LW; ++i) {
+        prio.at(GP + i);
+        step(GP + i, sA, sB, true, false);
+      }
+    }
+  };
   auto pipeline = [&](auto mode) {
     // Software pipeline: between two barriers a wave emits group g - 1 and
     // warps group g (their ring slots are distinct), so the emit's LDS reads
@@ -1242,10 +1351,17 @@ __device__ __forceinline__ void stream2_body(Args& a, const ShiftEntry* __restri
       }
     }
   };
-  if (interior)
-    pipeline(RowMode<true>{});
-  else
-    pipeline(RowMode<false>{});
+  if (circle) {
+    if (interior)
+      pipeline_circle(RowMode<true>{});
+    else
+      pipeline_circle(RowMode<false>{});
+  } else {
+    if (interior)
+      pipeline(RowMode<true>{});
+    else
+      pipeline(RowMode<false>{});
+  }
   __syncthreads();  // the ring becomes the reduction buffer
 
   red_s[t] = static_cast<double>(psum);
@@ -1570,6 +1686,12 @@ template <int WAVES>
 constexpr int stream_waves_per_eu() {
   return WAVES >= 8 ? 6 : 1;
 }
+// The variant-1 kernel's 4-row, 4-wave shape is launched with five waves per
+// SIMD at 512 x 512 (1280 workgroups); at four it ran 56.5 against 41.4 us.
+template <int TY, int WAVES>
+constexpr int stream2_waves_per_eu() {
+  return TY == 4 && WAVES == 4 ? 5 : stream_waves_per_eu<WAVES>();
+}
 
 template <typename T, int R, int TY, int WAVES, int NBUF>
 __global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(stream_waves_per_eu<WAVES>())))
@@ -1591,14 +1713,14 @@ void stream_batch(const StepArgs* __restrict__ jobs,
 }
 
 template <typename T, int R, int TY, int WAVES, int NBUF>
-__global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(stream_waves_per_eu<WAVES>())))
+__global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(stream2_waves_per_eu<TY, WAVES>())))
 void stream2_single(StepArgs a, ShiftArgs tab) {
   const int n = a.tiles_x * a.tiles_y * a.chunks;
   stream2_body<T, R, TY, WAVES, NBUF>(a, a.table ? a.table : tab.e, xcd_remap(blockIdx.x, n), n);
 }
 
 template <typename T, int R, int TY, int WAVES, int NBUF>
-__global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(stream_waves_per_eu<WAVES>())))
+__global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(stream2_waves_per_eu<TY, WAVES>())))
 void stream2_batch(const StepArgs* __restrict__ jobs, const int32_t* __restrict__ first, int njobs, int total) {
   const int g = xcd_remap(blockIdx.x, total);
   const int j = find_job(first, njobs, g);
