@@ -85,20 +85,46 @@ __global__ __launch_bounds__(kThThreads) void aniso_taps_kernel(AnisoArgs a) {
   for (int e = t; e < d * d; e += kThThreads, ++u) a.taps[k * d * d + e] = static_cast<float>(w[u] / z);
 }
 
+// Raw-buffer reads of one stored value (zero outside the descriptor).
+template <typename T>
+__device__ inline float ld_buf(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff);
+template <>
+__device__ inline float ld_buf<float>(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+template <>
+__device__ inline float ld_buf<__bf16>(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+  return __uint_as_float(static_cast<uint32_t>(__builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0)) << 16);
+}
+template <>
+__device__ inline float ld_buf<_Float16>(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+  return static_cast<float>(__builtin_bit_cast(_Float16, __builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0)));
+}
+// Offsets into one heading plane below 1 GiB: a row part below 2^30, or 2^30
+// for a row outside the grid, plus a column part below 2^30, or 2^31 for a
+// column outside; the sum is out of the plane's range exactly when either is.
+constexpr uint32_t kThRowOut = 1u << 30;
+constexpr uint32_t kThColOut = 1u << 31;
+
 // Warp, pre-blur mask and circular theta blur into the FP32 scratch.  Grid
 // (pitch / kThThreads, H): one cell per thread, streaming through the
 // channels.  Each channel's warped value is computed once and kept in a
-// shift register of the last 2 rth + 1 channels; output channel k is emitted
-// when channel k + rth has arrived.  The next channel's four source values
-// are loaded before the current one is combined.
-template <typename T>
+// shift register of the last 2 RTH + 1 channels; output channel k is emitted
+// when channel k + RTH has arrived.  The next channel's four source values
+// are loaded before the current one is combined.  BUF (planes below 1 GiB):
+// the source values come through a buffer descriptor per plane, the two row
+// offsets in scalar registers (the row is the workgroup's), so only the two
+// column tests run per lane.
+template <typename T, int RTH, bool BUF>
 __global__ __launch_bounds__(kThThreads) void aniso_theta_kernel(AnisoArgs a) {
+  constexpr int NTAP = 2 * RTH + 1;
+  constexpr int EB = static_cast<int>(sizeof(T));
   __shared__ int snx[kMaxTheta], sny[kMaxTheta];
   __shared__ float sfx[kMaxTheta], sfy[kMaxTheta];
   const int t = threadIdx.x;
   const int i = blockIdx.x * kThThreads + t;
   const int j = blockIdx.y;
-  const int n = a.n_theta, rth = a.rth, nt = 2 * a.rth + 1;
+  const int n = a.n_theta, rth = RTH;
   for (int k = t; k < n; k += kThThreads) channel_shift(a, k, snx[k], sny[k], sfx[k], sfy[k]);
   __syncthreads();
   if (i >= a.pitch) return;
@@ -109,9 +135,30 @@ __global__ __launch_bounds__(kThThreads) void aniso_theta_kernel(AnisoArgs a) {
   const float mp = inside ? a.mpre[static_cast<int64_t>(j) * a.pitch + i] * scale : 0.f;
   float* __restrict__ out = a.tmp + static_cast<int64_t>(j) * a.pitch + i;
   // the four source values of channel c (zero outside the grid) and their weights
+  const uint32_t row_bytes = static_cast<uint32_t>(a.pitch) * EB;
+  const uint32_t plane_bytes = static_cast<uint32_t>(a.sstride) * EB;  // below 2^30 when BUF
   auto fetch = [&](int c, float v[4]) {
-    const int nx = snx[c], ny = sny[c];
+    const int nx = __builtin_amdgcn_readfirstlane(snx[c]), ny = __builtin_amdgcn_readfirstlane(sny[c]);
     const T* plane = bin + static_cast<int64_t>(c) * a.sstride;
+    if constexpr (BUF) {
+      const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+          const_cast<T*>(plane), static_cast<short>(0), static_cast<int>(plane_bytes), 0x00020000);
+      uint32_t coff[2];
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const int ii = i - nx - q;
+        coff[q] = static_cast<unsigned>(ii) < static_cast<unsigned>(a.W) ? static_cast<uint32_t>(ii) * EB : kThColOut;
+      }
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        const int jj = j - ny - b;
+        const uint32_t roff = static_cast<unsigned>(jj) < static_cast<unsigned>(a.H) ? static_cast<uint32_t>(jj) * row_bytes
+                                                                                     : kThRowOut;
+#pragma unroll
+        for (int q = 0; q < 2; ++q) v[2 * b + q] = ld_buf<T>(rs, coff[q], roff);
+      }
+      return;
+    }
 #pragma unroll
     for (int b = 0; b < 2; ++b) {
       const int jj = j - ny - b;
@@ -127,9 +174,9 @@ __global__ __launch_bounds__(kThThreads) void aniso_theta_kernel(AnisoArgs a) {
       }
     }
   };
-  float ring[kMaxTaps];
+  float ring[NTAP];
 #pragma unroll
-  for (int l = 0; l < kMaxTaps; ++l) ring[l] = 0.f;
+  for (int l = 0; l < NTAP; ++l) ring[l] = 0.f;
   const int total = n + 2 * rth;  // channels -rth .. n - 1 + rth
   int c = (n - rth % n) % n;
   float v[4];
@@ -141,13 +188,13 @@ __global__ __launch_bounds__(kThThreads) void aniso_theta_kernel(AnisoArgs a) {
     fetch(cn, vn);  // past the last channel this reads a valid plane and is discarded
     const float s = ((1.f - fx) * v[0] + fx * v[1]) * (1.f - fy) + ((1.f - fx) * v[2] + fx * v[3]) * fy;
 #pragma unroll
-    for (int l = kMaxTaps - 1; l > 0; --l) ring[l] = ring[l - 1];
+    for (int l = NTAP - 1; l > 0; --l) ring[l] = ring[l - 1];
     ring[0] = inside ? s * mp : 0.f;
     if (e >= 2 * rth) {
       // ring[l] holds channel (k + rth - l): output k = e - 2 rth
       float acc = 0.f;
 #pragma unroll
-      for (int l = 0; l < kMaxTaps; ++l) acc += (l < nt ? a.gth[l] : 0.f) * ring[l];
+      for (int l = 0; l < NTAP; ++l) acc += a.gth[l] * ring[l];
       out[static_cast<int64_t>(e - 2 * rth) * a.sstride] = acc;
     }
     c = cn;
@@ -338,7 +385,24 @@ hipError_t launch_typed(const AnisoArgs& a, hipStream_t s) {
   const dim3 g1((a.pitch + kThThreads - 1) / kThThreads, a.H);
   const dim3 g2((a.W + kXyTx - 1) / kXyTx, (a.H + kXyTy - 1) / kXyTy, (a.n_theta + kXyChannels - 1) / kXyChannels);
   hipLaunchKernelGGL(aniso_taps_kernel, dim3(a.n_theta), dim3(kThThreads), 0, s, a);
-  hipLaunchKernelGGL(aniso_theta_kernel<T>, g1, dim3(kThThreads), 0, s, a);
+  const bool buf = static_cast<uint64_t>(a.sstride) * sizeof(T) < (static_cast<uint64_t>(1) << 30);
+#define MCL_THETA(R_)                                                                         \
+  case R_:                                                                                    \
+    if (buf)                                                                                  \
+      hipLaunchKernelGGL((aniso_theta_kernel<T, R_, true>), g1, dim3(kThThreads), 0, s, a);  \
+    else                                                                                      \
+      hipLaunchKernelGGL((aniso_theta_kernel<T, R_, false>), g1, dim3(kThThreads), 0, s, a); \
+    break;
+  static_assert(kMaxRadius == 4, "instantiate aniso_theta_kernel for every theta radius");
+  switch (a.rth) {
+    MCL_THETA(0)
+    MCL_THETA(1)
+    MCL_THETA(2)
+    MCL_THETA(3)
+    MCL_THETA(4)
+    default: return hipErrorInvalidValue;
+  }
+#undef MCL_THETA
   switch (a.rxy) {
     case 0: hipLaunchKernelGGL((aniso_xy_kernel<T, 0>), g2, dim3(kXyThreads), 0, s, a); break;
     case 1: hipLaunchKernelGGL((aniso_xy_kernel<T, 1>), g2, dim3(kXyThreads), 0, s, a); break;
