@@ -56,3 +56,25 @@ def test_circle_schedule_stores_what_the_chunked_one_stores(storage):
             assert np.array_equal(a, b), f"step {t}: stored beliefs differ"
             ln = chunked.info().log_norm
             assert circle.info().log_norm == pytest.approx(ln, abs=1e-5 + 1e-6 * abs(ln))
+
+
+def test_circle_schedule_in_a_batch_equals_single_steps():
+    # the batched step kernels take the schedule per job: filters of several
+    # heading counts and storage types stepped in shared launches store
+    # bitwise what they store stepped alone
+    from paper_1910_00572_amd import mcl
+    occ = bsp_rooms(72, 58, seed=25)
+    m = mcl.Map(occ, 0.1, 1.0)
+    specs = [(14, "f32"), (30, "bf16"), (37, "f16"), (30, "f32")]
+    solo = [mcl.Filter(m, t, 1.0, storage=st, launch_shape=CIRCLE) for t, st in specs]
+    batch = [mcl.Filter(m, t, 1.0, storage=st, launch_shape=CIRCLE) for t, st in specs]
+    ws = mcl.BatchWorkspace(len(specs))
+    odo = [_odometry(26 + i) for i in range(len(specs))]
+    say("[circle] batch against single steps")
+    for t in range(12):
+        for i, f in enumerate(solo):
+            f.step_odometry(*odo[i][t])
+        mcl.step_batch(batch, np.stack([o[t] for o in odo]), ws)
+    for a, b in zip(solo, batch):
+        assert np.array_equal(stored_belief(a), stored_belief(b))
+        assert a.info().log_norm == b.info().log_norm
