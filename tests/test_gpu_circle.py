@@ -78,3 +78,13 @@ def test_circle_schedule_in_a_batch_equals_single_steps():
     for a, b in zip(solo, batch):
         assert np.array_equal(stored_belief(a), stored_belief(b))
         assert a.info().log_norm == b.info().log_norm
+
+
+def test_circle_schedule_with_jumps_past_the_halo():
+    # 30-cell jumps up and down the map: slices whose first source row lies
+    # past the last grid row (an empty descriptor in the unchecked loop) and
+    # far above the first (the checked loop), against the oracle
+    occ = bsp_rooms(80, 62, seed=27)
+    odo = np.array([[0.0, 3.0, 0.1], [0.2, -3.0, -0.2], [-3.0, 0.4, 0.3], [3.1, 0.0, 0.0],
+                    [0.0, 2.6, 0.5], [0.1, -2.9, 0.0]])
+    _run_pair(occ, 0.1, 30, 1.0, 1.0, odo, tag="circle jumps", launch_shape=CIRCLE)
