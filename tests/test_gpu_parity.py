@@ -161,6 +161,19 @@ def test_shifts_beyond_the_halo():
     _run_pair(occ, 0.1, 8, 0.5, 0.5, odo, tag="bigshift")
 
 
+@pytest.mark.parametrize("shape", [(0, 16, 512, 1, 1, 0), (0, 16, 512, 1, 1, 0, 4), (0, 4, 256, 2, 2, 1)],
+                         ids=lambda s: ",".join(map(str, s)))
+def test_jumps_past_the_grid_edge_at_streaming_shapes(shape):
+    # 30-cell jumps up, down and sideways: the streaming kernels address a
+    # slice's rows from its first row where no channel's rows start above the
+    # grid and check every row elsewhere; slices that start past the last row
+    # or far above the first must read zeros either way
+    occ = bsp_rooms(80, 62, seed=27)
+    odo = np.array([[0.0, 3.0, 0.1], [0.2, -3.0, -0.2], [-3.0, 0.4, 0.3], [3.1, 0.0, 0.0],
+                    [0.0, 2.6, 0.5], [0.1, -2.9, 0.0]])
+    _run_pair(occ, 0.1, 30, 1.0, 1.0, odo, tag=f"jumps {shape}", launch_shape=shape)
+
+
 def test_zero_noise_integer_shift_is_exact():
     occ = np.zeros((20, 24), np.uint8)
     occ[0, :] = occ[-1, :] = occ[:, 0] = occ[:, -1] = 1
