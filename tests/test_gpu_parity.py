@@ -119,6 +119,28 @@ def test_anisotropic_noise(case):
               tag=f"aniso {case}")
 
 
+@pytest.mark.parametrize("storage", ["f32", "bf16"])
+def test_anisotropic_jumps_past_the_grid_edge(storage):
+    # 30-cell jumps: the warp pass reads each source through a per-plane
+    # buffer descriptor whose range check must return zeros for rows above
+    # and below the grid and columns beside it (FP32 against the oracle;
+    # BF16 must keep the stored belief of its own FP32 run within its rounding)
+    occ = bsp_rooms(80, 62, seed=29)
+    odo = np.array([[0.0, 3.0, 0.1], [0.2, -3.0, -0.2], [-3.0, 0.4, 0.3], [3.1, 0.0, 0.0],
+                    [0.0, 2.6, 0.5], [0.1, -2.9, 0.0]])
+    if storage == "f32":
+        _run_pair(occ, 0.1, 20, 1.1, 0.8, odo, flags=3 | 32, sigma_lateral=0.5, tag="aniso jumps")
+        return
+    _, f32 = make_gpu(occ, 0.1, 20, 1.1, 0.8, flags=3 | 32, sigma_lateral=0.5)
+    _, b16 = make_gpu(occ, 0.1, 20, 1.1, 0.8, flags=3 | 32, sigma_lateral=0.5, storage="bf16")
+    for u, v, w in odo:
+        f32.step_odometry(u, v, w)
+        b16.step_odometry(u, v, w)
+    a, b = f32.read_belief()[0], b16.read_belief()[0]
+    assert float(np.abs(a.astype(np.float64) - b).sum()) <= 1e-2
+    assert in_tie_set(b16.read_belief()[1].as_tuple(), a.astype(np.float64), 2.0 ** -7)
+
+
 def test_anisotropic_isotropic_limit_matches_the_fused_step():
     # sigma across = sigma along: the two-pass path computes the separable step
     occ = bsp_rooms(56, 44, seed=77)
