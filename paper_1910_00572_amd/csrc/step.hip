@@ -622,6 +622,26 @@ __device__ inline float from_right(float v) {
   return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x130, 0xf, 0xf, true));
 }
 
+// x blur of one row held one column per lane, sum over m of g[R + m] v(x + m)
+// with g[R + m] = g[R - m].  Each side is summed Horner-style towards the
+// centre, a_m = a_{m+1}(shifted one lane) + g[R + m] v, so that every lane
+// shift is folded into an add (no separate lane moves); the products and
+// sums are rounded separately so the shifts stay on the added operand.
+template <int R>
+__device__ inline float x_blur_shifted_sums(float v, const float (&g)[2 * R + 1]) {
+#pragma clang fp contract(off)
+  float gv[R + 1];
+#pragma unroll
+  for (int m = 0; m <= R; ++m) gv[m] = g[R + m] * v;
+  float al = gv[R], ar = gv[R];
+#pragma unroll
+  for (int m = R - 1; m >= 1; --m) {
+    al = from_left(al) + gv[m];
+    ar = from_right(ar) + gv[m];
+  }
+  return (from_left(al) + gv[0]) + from_right(ar);
+}
+
 template <typename T, int R, int TY, int WAVES, int NBUF, typename Args = const StepArgs>
 __device__ __forceinline__ void stream_body(Args& a, const ShiftEntry* __restrict__ tab, const int blk,
                                             const int nblk) {
@@ -798,13 +818,21 @@ __device__ __forceinline__ void stream_body(Args& a, const ShiftEntry* __restric
         float yv = gx[0] * vv[o];
 #pragma unroll
         for (int l = 1; l < TAPS; ++l) yv = fmaf(gx[l], vv[o + l], yv);
-        float p = gx[R] * yv;
-        float dl = yv, dr = yv;
+        // 16-bit storage is bound by vector issue at this shape: the form
+        // without lane moves saves 5 % of its VALU work (FP32, closer to its
+        // memory limit, runs no faster with it and keeps the fused form)
+        float p;
+        if constexpr (sizeof(T) == 2) {
+          p = x_blur_shifted_sums<R>(yv, gx);
+        } else {
+          p = gx[R] * yv;
+          float dl = yv, dr = yv;
 #pragma unroll
-        for (int m = 1; m <= R; ++m) {
-          dl = from_left(dl);
-          dr = from_right(dr);
-          p = fmaf(gx[R + m], dl + dr, p);
+          for (int m = 1; m <= R; ++m) {
+            dl = from_left(dl);
+            dr = from_right(dr);
+            p = fmaf(gx[R + m], dl + dr, p);
+          }
         }
         p4[q] = p;
       }
