@@ -627,12 +627,14 @@ __device__ inline float from_right(float v) {
 // centre, a_m = a_{m+1}(shifted one lane) + g[R + m] v, so that every lane
 // shift is folded into an add (no separate lane moves); the products and
 // sums are rounded separately so the shifts stay on the added operand.
-template <int R>
+// With UNIT the centre tap is taken as one (the caller scaled the taps).
+template <int R, bool UNIT>
 __device__ inline float x_blur_shifted_sums(float v, const float (&g)[2 * R + 1]) {
 #pragma clang fp contract(off)
   float gv[R + 1];
+  gv[0] = UNIT ? v : g[R] * v;
 #pragma unroll
-  for (int m = 0; m <= R; ++m) gv[m] = g[R + m] * v;
+  for (int m = 1; m <= R; ++m) gv[m] = g[R + m] * v;
   float al = gv[R], ar = gv[R];
 #pragma unroll
   for (int m = R - 1; m >= 1; --m) {
@@ -712,11 +714,27 @@ __device__ __forceinline__ void stream_body(Args& a, const ShiftEntry* __restric
     pfx[k] = e.fx;
     pfy[k] = e.fy;
   }
+  // 16-bit storage is bound by vector issue at this kernel's shapes: its
+  // three blurs run with the centre tap scaled to one (one multiply fewer
+  // per blur and row), and the product of the three centre taps moves into
+  // the post-blur weights
+  constexpr bool kUnitCentre = sizeof(T) == 2;
   float gx[TAPS], gt[TAPS];
 #pragma unroll
   for (int l = 0; l < TAPS; ++l) {
     gx[l] = a.gxy[l];
     gt[l] = a.gth[l];
+  }
+  float centre = 1.f;
+  if constexpr (kUnitCentre) {
+    const float cx = gx[R], ct = gt[R];
+    centre = cx * cx * ct;
+#pragma unroll
+    for (int l = 0; l < TAPS; ++l) {
+      // uniform values: kept in scalar registers
+      gx[l] = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, gx[l] / cx)));
+      gt[l] = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, gt[l] / ct)));
+    }
   }
   const bool xin = x >= 0 && x < pitch;
   float mreg[NS];
@@ -730,7 +748,7 @@ __device__ __forceinline__ void stream_body(Args& a, const ShiftEntry* __restric
 #pragma unroll
   for (int o = 0; o < TY; ++o) {
     const int y = y0 + o;
-    wreg[o] = (out_lane && y < H) ? a.wt[static_cast<int64_t>(y) * pitch + x] * scale : 0.f;
+    wreg[o] = (out_lane && y < H) ? a.wt[static_cast<int64_t>(y) * pitch + x] * scale * centre : 0.f;
   }
   // store offset of this lane (out of range for lanes that hold no output)
   const uint32_t soff = out_lane ? static_cast<uint32_t>(x) * EB : kColOut;
@@ -815,15 +833,23 @@ __device__ __forceinline__ void stream_body(Args& a, const ShiftEntry* __restric
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int o = o4 + q;
-        float yv = gx[0] * vv[o];
+        float yv;
+        if constexpr (kUnitCentre) {
+          yv = vv[o + R];
 #pragma unroll
-        for (int l = 1; l < TAPS; ++l) yv = fmaf(gx[l], vv[o + l], yv);
+          for (int l = 0; l < TAPS; ++l)
+            if (l != R) yv = fmaf(gx[l], vv[o + l], yv);
+        } else {
+          yv = gx[0] * vv[o];
+#pragma unroll
+          for (int l = 1; l < TAPS; ++l) yv = fmaf(gx[l], vv[o + l], yv);
+        }
         // 16-bit storage is bound by vector issue at this shape: the form
         // without lane moves saves 5 % of its VALU work (FP32, closer to its
         // memory limit, runs no faster with it and keeps the fused form)
         float p;
         if constexpr (sizeof(T) == 2) {
-          p = x_blur_shifted_sums<R>(yv, gx);
+          p = x_blur_shifted_sums<R, kUnitCentre>(yv, gx);
         } else {
           p = gx[R] * yv;
           float dl = yv, dr = yv;
@@ -871,8 +897,15 @@ __device__ __forceinline__ void stream_body(Args& a, const ShiftEntry* __restric
 #pragma unroll
       for (int q = 0; q < RB / 4; ++q) {
         float acc[4] = {0.f, 0.f, 0.f, 0.f};
+        if constexpr (kUnitCentre) {
+          acc[0] = rv[q][R].x;
+          acc[1] = rv[q][R].y;
+          acc[2] = rv[q][R].z;
+          acc[3] = rv[q][R].w;
+        }
 #pragma unroll
         for (int l = 0; l < TAPS; ++l) {
+          if (kUnitCentre && l == R) continue;
           acc[0] = fmaf(gt[l], rv[q][l].x, acc[0]);
           acc[1] = fmaf(gt[l], rv[q][l].y, acc[1]);
           acc[2] = fmaf(gt[l], rv[q][l].z, acc[2]);
