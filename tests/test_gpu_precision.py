@@ -12,7 +12,7 @@ import pytest
 
 import oracle as O
 from gen import bsp_rooms, random_odometry, rooms_and_corridors, smooth_trajectory
-from tests.gpu_harness import in_tie_set, l1_err, make_gpu, needs_gpu, oracle_params, peak_err, say
+from tests.gpu_harness import in_tie_set, l1_err, make_gpu, needs_gpu, oracle_params, peak_err, say, stored_belief
 
 pytestmark = [pytest.mark.gpu, needs_gpu]
 
@@ -172,3 +172,37 @@ def test_reduced_precision_at_the_large_map_shapes():
                 assert abs(ln - st_o.log_norm) < 1e-2
     for key, wv in worst.items():
         say(f"[precision] {key}: worst L1 over 200 steps {wv:.3e}")
+
+
+@pytest.mark.parametrize("sigma", [0.3, 0.6, 1.3], ids=lambda s: f"sigma{s}")
+@pytest.mark.parametrize("storage", ["bf16", "f16"])
+def test_reduced_precision_large_map_shape_at_every_radius(storage, sigma):
+    # the large-map launch shape (16-row strips, 8 waves, one slice buffer)
+    # in 16-bit storage runs its blurs in forms of its own (x blur summed
+    # towards the centre, centre taps scaled to one); kernel radii 1, 2 and
+    # 4 in x, y and theta, 40 steps against the FP64 oracle; the batched
+    # kernel of the same shape stores bitwise what the single one stores
+    from paper_1910_00572_amd import mcl
+    occ = bsp_rooms(96, 80, seed=61)
+    odo = random_odometry(40, seed=62, max_step_m=0.25) - np.array([0.12, 0.12, 0.0])
+    n_theta = 24
+    shape = (0, 16, 512, 1, 1, 0, 4)
+    p = oracle_params(n_theta, 0.1, sigma, sigma)
+    m, f = make_gpu(occ, 0.1, n_theta, sigma, sigma, storage=storage, launch_shape=shape)
+    fb = mcl.Filter(m, n_theta, sigma, storage=storage, launch_shape=shape)
+    ws = mcl.BatchWorkspace(1)
+    st = O.init_uniform(occ, n_theta)
+    M = O.free_mask(occ)
+    say(f"[precision] large-map shape, {storage}, sigma {sigma}")
+    for t, (u, v, w) in enumerate(odo):
+        f.step_odometry(u, v, w)
+        mcl.step_batch([fb], np.array([[u, v, w]]), ws)
+        st = O.step(st, occ, p, u, v, w, M=M)
+        if t % 10 == 9:
+            b, pose, _, ln = f.read_belief()
+            l1 = l1_err(b, st.B)
+            assert l1 <= L1_TOL, f"step {t}: L1 {l1:.3e}"
+            assert in_tie_set(pose.as_tuple(), st.B, TIE_TAU), f"step {t}: argmax {pose.as_tuple()}"
+            assert abs(ln - st.log_norm) < 1e-2
+    assert np.array_equal(stored_belief(f), stored_belief(fb))
+    assert f.info().log_norm == fb.info().log_norm
